@@ -1,0 +1,153 @@
+"""Seeded synthetic workloads for the vector-OMT solver.
+
+This module holds no arithmetic of the transport method: it only draws the
+input densities (cell masses, App. A) and names the channel graphs and
+parameters of each workload.  Both the HIP path and the oracle are fed from
+here, so it imports nothing else from this package.
+
+The paper's own inputs (colour images of Sec. 8.1) are not available; smooth
+Gaussian-mixture fields of the same kind stand in for them:
+
+* for every channel ``c`` and bump ``b``: centre uniform over the grid,
+  width ``sigma`` uniform in ``[sig_lo, sig_hi]`` pixels, amplitude uniform in
+  ``[0.5, 1.5]``; the channel is the sum of its bumps plus a constant floor;
+* the whole density is rescaled to unit total mass (Sec. 3.2), or, when
+  ``channel_mass`` is given, channel ``c`` is rescaled to carry
+  ``channel_mass[c] / sum(channel_mass)``;
+* the generator is numpy's PCG64 seeded by ``SeedSequence([cfg, pair, side])``
+  with ``side`` 0 for rho0 and 1 for rho1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+TRIANGLE = np.array([[0, 1], [0, 2], [1, 2]], dtype=np.int32)
+
+
+def path_edges(k: int) -> np.ndarray:
+    """Edges (c, c+1) of the path graph on k channels."""
+    return np.array([[c, c + 1] for c in range(k - 1)], dtype=np.int32).reshape(-1, 2)
+
+
+def complete_edges(k: int) -> np.ndarray:
+    """All pairs a < b in lexicographic order (the triangle for k = 3)."""
+    return np.array([[a, b] for a in range(k) for b in range(a + 1, k)], dtype=np.int32).reshape(-1, 2)
+
+
+def default_tau(m: int, n: int) -> float:
+    """Dual step used for a grid: 1 up to side 64, 3 above (the values the
+    paper tuned for its V-OMT grids, Table 'vecgrid1')."""
+    return 1.0 if max(m, n) <= 64 else 3.0
+
+
+def gaussian_mixture(m: int, n: int, k: int, bumps: int, sig_lo: float, sig_hi: float,
+                     floor: float, rng: np.random.Generator, channel_mass=None) -> np.ndarray:
+    """(m, n, k) float64 cell masses, unit total mass."""
+    ii = np.arange(m, dtype=np.float64)
+    jj = np.arange(n, dtype=np.float64)
+    out = np.zeros((m, n, k), dtype=np.float64)
+    for c in range(k):
+        acc = np.full((m, n), floor, dtype=np.float64)
+        for _ in range(bumps):
+            x0 = rng.uniform(0.0, m)
+            y0 = rng.uniform(0.0, n)
+            sig = rng.uniform(sig_lo, sig_hi)
+            amp = rng.uniform(0.5, 1.5)
+            gi = np.exp(-((ii - x0) ** 2) / (2.0 * sig * sig))
+            gj = np.exp(-((jj - y0) ** 2) / (2.0 * sig * sig))
+            acc += amp * np.outer(gi, gj)
+        out[:, :, c] = acc
+    if channel_mass is None:
+        out /= out.sum()
+    else:
+        cm = np.asarray(channel_mass, dtype=np.float64)
+        cm = cm / cm.sum()
+        for c in range(k):
+            out[:, :, c] *= cm[c] / out[:, :, c].sum()
+    return out
+
+
+def pair(cfg: int, pair_id: int, m: int, n: int, k: int, bumps: int, sig_lo: float, sig_hi: float,
+         floor: float, channel_mass0=None, channel_mass1=None):
+    """(rho0, rho1) for one workload pair, drawn as described above."""
+    r0 = np.random.default_rng(np.random.SeedSequence([cfg, pair_id, 0]))
+    r1 = np.random.default_rng(np.random.SeedSequence([cfg, pair_id, 1]))
+    rho0 = gaussian_mixture(m, n, k, bumps, sig_lo, sig_hi, floor, r0, channel_mass0)
+    rho1 = gaussian_mixture(m, n, k, bumps, sig_lo, sig_hi, floor, r1, channel_mass1)
+    return rho0, rho1
+
+
+# ------------------------------------------------------------- workloads
+
+def small_fp64(pair_id: int = 0, m: int = 32, n: int = 32):
+    """32x32, k=3 triangle, alpha 1, FP64, 4 bumps per channel with sigma in
+    [2, 6] px and no floor; 10,000 iterations."""
+    rho0, rho1 = pair(1, pair_id, m, n, 3, 4, 2.0, 6.0, 0.0)
+    return dict(name=f"vomt_{m}x{n}_k3_triangle_fp64", rho0=rho0, rho1=rho1, edges=TRIANGLE,
+                alpha=1.0, tau=default_tau(m, n), iters=10000, dtype="f64")
+
+
+def rgb_256(alpha: float = 1.0, pair_id: int = None, m: int = 256, n: int = 256):
+    """256x256, k=3 triangle, 8 bumps per channel, sigma in [8, 32] px, floor
+    1e-3; one pair per alpha in {0.5, 1, 4}; solved to 1e-5 residual."""
+    if pair_id is None:
+        pair_id = {0.5: 0, 1.0: 1, 4.0: 2}.get(float(alpha), 0)
+    rho0, rho1 = pair(2, pair_id, m, n, 3, 8, 8.0 * m / 256, 32.0 * m / 256, 1e-3)
+    return dict(name=f"vomt_{m}x{n}_k3_triangle_a{alpha:g}", rho0=rho0, rho1=rho1, edges=TRIANGLE,
+                alpha=float(alpha), tau=default_tau(m, n), tol=1e-5, dtype="f32")
+
+
+def path8_1024(m: int = 1024, n: int = 1024, k: int = 8):
+    """1024x1024, k=8 path graph (7 edges), alpha 1, 16 bumps per channel,
+    sigma in [16, 64] px, floor 1e-3.  rho0 puts mass proportional to c+1 in
+    channel c and rho1 mass proportional to k-c, so the transfer w between
+    channels is active; 20,000 iterations."""
+    s = m / 1024.0
+    rho0, rho1 = pair(3, 0, m, n, k, 16, max(16.0 * s, 1.0), max(64.0 * s, 2.0), 1e-3,
+                      channel_mass0=[c + 1 for c in range(k)],
+                      channel_mass1=[k - c for c in range(k)])
+    return dict(name=f"vomt_{m}x{n}_k{k}_path", rho0=rho0, rho1=rho1, edges=path_edges(k),
+                alpha=1.0, tau=default_tau(m, n), iters=20000, dtype="f32")
+
+
+BATCH_SIDES = (64, 128, 192, 256, 384, 512)
+
+
+def batch_spec(n_pairs: int = 96, sides=BATCH_SIDES):
+    """Shapes and parameters of the batched workload: side uniform over
+    ``sides``, k uniform over {1, 3} (triangle for 3), alpha uniform in
+    [0.5, 4]."""
+    specs = []
+    for p in range(n_pairs):
+        rng = np.random.default_rng(np.random.SeedSequence([4, p, 2]))
+        side = int(rng.choice(sides))
+        k = int(rng.choice([1, 3]))
+        alpha = float(rng.uniform(0.5, 4.0))
+        specs.append(dict(pair=p, side=side, k=k, alpha=alpha))
+    return specs
+
+
+def batch_pair(spec):
+    """(rho0, rho1, edges, alpha, tau) of one batched pair: 8 bumps with sigma
+    in [side/32, side/8], floor 1e-3."""
+    side, k = spec["side"], spec["k"]
+    rho0, rho1 = pair(4, spec["pair"], side, side, k, 8, side / 32.0, side / 8.0, 1e-3)
+    edges = TRIANGLE if k == 3 else np.zeros((0, 2), np.int32)
+    return dict(name=f"batch{spec['pair']}_{side}_k{k}", rho0=rho0, rho1=rho1, edges=edges,
+                alpha=spec["alpha"], tau=default_tau(side, side), tol=1e-5, dtype="f32")
+
+
+def loss_512(pair_id: int, m: int = 512, n: int = 512):
+    """512x512, k=3 triangle, alpha 1 pair for the differentiable loss (8 per
+    batch), 8 bumps, sigma in [16, 64] px, floor 1e-3; solved to 1e-6."""
+    s = m / 512.0
+    rho0, rho1 = pair(5, pair_id, m, n, 3, 8, 16.0 * s, 64.0 * s, 1e-3)
+    return dict(name=f"loss_{m}x{n}_k3_{pair_id}", rho0=rho0, rho1=rho1, edges=TRIANGLE,
+                alpha=1.0, tau=default_tau(m, n), tol=1e-6, dtype="f32")
+
+
+def random_pair(seed: int, m: int, n: int, k: int, bumps: int = 3, floor: float = 1e-3):
+    """Small generic pair for tests (cfg id 100)."""
+    lo = max(1.0, min(m, n) / 12.0)
+    hi = max(2.0, min(m, n) / 4.0)
+    return pair(100, seed, m, n, k, bumps, lo, hi, floor)

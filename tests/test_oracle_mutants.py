@@ -1,0 +1,42 @@
+"""The oracle's pins must be able to fail: plant one plausible mistake at a
+time in a copy of the oracle (on the CPU), rebuild it, and check that the pin
+suite rejects every copy."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "omt_oracle.c")
+
+MUTANTS = [
+    ("wrong neighbour in div_x", "double yl = (j > 0) ? uy[I3(i, j - 1, c, n, k)]", "double yl = (j > 1) ? uy[I3(i, j - 2 + 1, c, n, k)]"),
+    ("dropped extrapolation", "W->bx[q] = 2.0 * ux1[q] - ux[q];", "W->bx[q] = ux1[q];"),
+    ("wrong u threshold", "orc_shrink_u(p->unorm, k, bx, by, p->mu);", "orc_shrink_u(p->unorm, k, bx, by, 0.9 * p->mu);"),
+    ("sign of div_G", "x[c] = -s;", "x[c] = s;"),
+    ("1/mu on the w block of R", "out[0] = su / p->mu + (l > 0 ? sw / p->nu", "out[0] = su / p->mu + (l > 0 ? sw / p->mu"),
+    ("dropped source term", "phi1[q] = phi[q] + p->tau * (W->dx[q] + W->dg[q] + f[q]);", "phi1[q] = phi[q] + p->tau * (W->dx[q] + W->dg[q]);"),
+    ("transposed gradient", "gy[I3(i, j, c, n, k)] = (j < n - 1) ? (phi[I3(i, j + 1, c, n, k)]", "gy[I3(i, j, c, n, k)] = (j < n - 1) ? (phi[I3(i + 1 < m ? i + 1 : i, j, c, n, k)]"),
+    ("w threshold without alpha", "orc_shrink_w(p->wnorm, l, b, p->alpha * p->nu);", "orc_shrink_w(p->wnorm, l, b, p->nu);"),
+    ("mu rule of S-OMT used for V-OMT", "p->mu = p->h * p->h / (32.0 * p->tau);", "p->mu = p->h * p->h / (16.0 * p->tau);"),
+]
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_reject_mutant(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert old in src, f"pattern for '{name}' not found"
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new, 1))
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-o", str(so), str(mut), "-lm"],
+                   check=True)
+    env = dict(os.environ, OMT_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_operators.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant '{name}' survived the pins:\n{r.stdout[-2000:]}"
