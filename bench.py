@@ -1,0 +1,148 @@
+"""Throughput of the fused PDHG step on one MI355X.
+
+Workload: vector OMT on a 1024 x 1024 grid, k = 8 channels on a path graph
+(7 edges), alpha 1, FP32 iterates with FP64 reductions, seeded 16-bump
+Gaussian mixtures with mass moved between channels (see
+``paper_1712_10279_amd/inputs.py``).  One step is one PDHG iteration of the
+whole path (gradient, both shrinks, extrapolation, divergences, dual ascent)
+over the grid; the solve takes its residual/objective check every 64
+iterations inside the timed region, as a real solve does.
+
+Prints one JSON line.  ``value`` is cell-iterations/s (cells = grid pixels,
+each carrying all k channels and l edges) with the inputs resident in HBM.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=640)
+    ap.add_argument("--size", type=int, default=1024, help="grid side (default: the 1024 x 1024 workload)")
+    ap.add_argument("--tblock", type=int, default=0, help="iterations per HBM pass (0: library default)")
+    ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0: library default)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations for the CPU baseline (0: auto)")
+    ap.add_argument("--timing-launches", type=int, default=200)
+    return ap.parse_args()
+
+
+def _kernel_hash():
+    h = hashlib.sha256()
+    for f in ("step.hip", "omt_kernels.h"):
+        with open(os.path.join(ROOT, "paper_1712_10279_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(tblock, size):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source and the same launch shape."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(f"T{tblock}_n{size}")
+    if not e or e.get("kernel_sha") != _kernel_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(d, iters):
+    """The FP64 oracle, single-threaded, on the same grid for a few iterations."""
+    import oracle as O
+    p = O.Problem(d["rho0"].shape[0], d["rho0"].shape[1], d["rho0"].shape[2], edges=d["edges"],
+                  alpha=d["alpha"], tau=d["tau"])
+    f, _ = O.prepare_f(d["rho0"].astype("float32").astype("float64"), d["rho1"].astype("float32").astype("float64"),
+                       p.edges)
+    r = O.solve(p, f, iters, 0.0, 1 << 30)
+    cells = p.m * p.n * iters
+    return {"value": cells / r["wall_s"], "unit": "cell-iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} FP64 iterations of the same {p.m}x{p.n}x{p.k} grid, single thread, "
+                      f"{r['wall_s']:.1f} s"}
+
+
+def main():
+    a = _parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {a.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1712_10279_amd import inputs as I
+    from paper_1712_10279_amd import omt
+
+    d = I.path8_1024(m=a.size, n=a.size)
+    m, n, k = d["rho0"].shape
+    l = len(d["edges"])
+    dev = torch.device("cuda:0")
+    r0 = torch.as_tensor(d["rho0"], dtype=torch.float32, device=dev)
+    r1 = torch.as_tensor(d["rho1"], dtype=torch.float32, device=dev)
+    s = omt.Solver(r0, r1, d["edges"], alpha=d["alpha"], tau=d["tau"], tblock=a.tblock, rows_per_wave=a.rows)
+    T = a.tblock if a.tblock > 0 else 1
+
+    if a.warmup:
+        s.solve(a.warmup, 0.0, 64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = s.solve(a.steps, 0.0, 64)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cells = m * n
+    value = cells * a.steps / dt
+
+    # dominant kernel: the fused step, timed with HIP events on its own stream
+    launches = max(1, a.timing_launches // T) * T
+    us = s.time_steps(T, a.rows, launches)
+    alg_bytes = (7 * k + 2 * l) * 4 * cells * T
+    achieved = alg_bytes / (us * 1e-6) / 1e9
+    V, _ = s.distance()
+
+    line = {
+        "metric": "PDHG cell-iterations/s",
+        "value": value,
+        "unit": "cell-iter/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": d["name"], "grid": [m, n], "channels": k, "edges": l, "graph": "path",
+                   "alpha": d["alpha"], "tau": d["tau"], "iterations": a.steps, "check_every": 64,
+                   "tblock": T, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(T, a.size),
+                     "kernel": "pdhg_step_kernel", "us_per_launch": us, "bytes_per_launch": alg_bytes},
+        "pixel_channel_iter_per_s": value * k,
+        "solve": {"primal": V, "residual": info["residual"], "rel_gap": info["rel_gap"],
+                  "mass_residual": info["mass_residual"]},
+    }
+    if not a.no_cpu:
+        iters = a.cpu_iters or max(2, int(40 * (1024 * 1024 * 8) / (cells * k)))
+        line["cpu_baseline"] = cpu_baseline(d, iters)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * omt.h -- C ABI of the MI355X (gfx950) solver for vector-valued optimal
+ * mass transport on a regular 2-D grid, after Ryu, Chen, Li and Osher,
+ * "Vector and Matrix Optimal Mass Transport: Theory, Algorithm, and
+ * Applications" (arXiv 1712.10279).
+ *
+ * The library solves the discrete vector-OMT problem of App. A,
+ *
+ *     V(rho0, rho1) = min ||u||_u + alpha ||w||_w
+ *                     s.t. div_x u + div_G w = rho0 - rho1,
+ *
+ * (the continuous problem and its dual are stated in Sec. 3.2) with the
+ * first-order primal-dual method of Sec. 7.2 (Sec. 7.1 when the channel graph
+ * has no edges):
+ *
+ *     u   <- shrink_u(u + mu grad_x phi, mu)
+ *     w   <- shrink_w(w + nu grad_G phi, alpha nu)
+ *     phi <- phi + tau (div_x(2u' - u) + div_G(2w' - w) + rho1 - rho0).
+ *
+ * Conventions shared by every call:
+ *   - Densities are cell masses (finite-volume integrals, App. A) in the
+ *     paper's layout: m x n x k, channel index fastest, row i (the paper's x)
+ *     slowest.  Grid spacing h = 1/(max(m,n)-1) unless given.
+ *   - Only rho1 - rho0 enters the discrete problem, so signed inputs are
+ *     accepted.  Per mass class (connected component of the channel graph)
+ *     the two masses must agree to 1e-6 relative; the difference that is
+ *     left is removed from rho1 - rho0 in FP64 before solving.
+ *   - Device pointers are HIP device addresses on the current device; host
+ *     pointers are ordinary process memory.  The caller owns every buffer.
+ *   - All device work of a handle is enqueued on the stream given at create.
+ *   - Every call returns an omt_status; no exception crosses the ABI.  A
+ *     human-readable detail of the last failure on the calling thread is
+ *     available from omt_last_error().
+ *   - Exported potential: Phi = -phi with its mean over each mass class
+ *     removed.  By the dual problem of Sec. 3.2, V = <phi, rho1 - rho0> at
+ *     optimum, so dV/drho0 = Phi and dV/drho1 = -Phi.
+ */
+#ifndef OMT_H
+#define OMT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OMT_OK = 0,
+    OMT_EINVAL = 1,        /* bad argument: sizes, NULL, NaN/Inf data, tau/alpha <= 0, ... */
+    OMT_EGRAPH = 2,        /* bad channel graph: a >= b, node out of range, duplicate edge, c <= 0 */
+    OMT_EMASS = 3,         /* the two densities carry different mass in some mass class */
+    OMT_ESTEP = 4,         /* given mu/nu violate tau mu 8/h^2 + tau nu lambda_max < 1 (Sec. 7.2) */
+    OMT_ENOMEM = 5,        /* workspace smaller than omt_workspace_bytes() */
+    OMT_EDEVICE = 6,       /* a HIP call failed */
+    OMT_ENOTCONV = 7,      /* tol not reached within max_iters; outputs are valid */
+    OMT_EDIVERGED = 8,     /* a check found a non-finite residual */
+    OMT_EUNSUPPORTED = 9   /* valid request this build does not provide (e.g. k > 8) */
+} omt_status;
+
+/* Norms of Sec. 6.2. */
+typedef enum {
+    OMT_U_L12 = 0, /* sum over channels of the Euclidean norm of (u_x, u_y): the default */
+    OMT_U_L1 = 1,  /* sum of absolute values of all 2k flux components            */
+    OMT_U_L2 = 2   /* Euclidean norm of all 2k flux components of a pixel          */
+} omt_unorm;
+
+typedef enum {
+    OMT_W_L1 = 0, /* sum of absolute values of the l transfers: the default */
+    OMT_W_L2 = 1  /* Euclidean norm of the l transfers of a pixel            */
+} omt_wnorm;
+
+typedef enum { OMT_F32 = 0, OMT_F64 = 1 } omt_dtype;
+
+/* Store the FP32 potential as an unevaluated sum hi + lo of two floats
+ * updated with an error-free addition, so that increments far below the
+ * FP32 spacing of phi are not lost. Ignored for OMT_F64. */
+#define OMT_FLAG_COMPENSATED_PHI 1u
+
+/* Largest channel count of this build. */
+#define OMT_MAX_CHANNELS 8
+
+typedef struct {
+    int32_t m, n;              /* grid rows and columns, each >= 2 */
+    int32_t k;                 /* channels, 1 <= k <= OMT_MAX_CHANNELS */
+    int32_t n_edges;           /* l >= 0 edges of the channel graph; 0 gives scalar OMT per channel */
+    const int32_t *edges;      /* host, 2*l node indices (a_e, b_e) with 0 <= a_e < b_e < k (Sec. 3.1) */
+    const double *edge_cost;   /* host, l costs c_e > 0 (edge weight 1/c_e^2), or NULL for all 1 */
+    double alpha;              /* > 0, weight of the channel transfer (Sec. 3.2) */
+    double tau;                /* > 0, dual step */
+    double mu, nu;             /* 0: the rule of Sec. 7.2 (mu = h^2/(32 tau), h^2/(16 tau) if l = 0;
+                                  nu = 1/(4 tau lambda_max(-Delta_G))); else checked as OMT_ESTEP says */
+    double h;                  /* 0: 1/(max(m,n)-1) */
+    int32_t unorm;             /* omt_unorm */
+    int32_t wnorm;             /* omt_wnorm */
+    int32_t dtype;             /* omt_dtype of inputs, outputs and iterates; reductions are FP64 */
+    uint32_t flags;            /* OMT_FLAG_* */
+    int32_t tblock;            /* iterations fused per pass over HBM (1, 2, 4, 8); 0 = tuned default */
+    int32_t rows_per_wave;     /* rows one wavefront streams through; 0 = tuned default */
+} omt_params;
+
+typedef struct {
+    int64_t iters;          /* iterations done by the solve */
+    double residual;        /* sqrt(R^k / R^0), R^k the fixed-point residual of Sec. 6.1 for the last
+                               step (with 1/nu on the w block) and R^0 = tau ||rho1 - rho0||^2 */
+    double primal;          /* ||u||_u + alpha ||w||_w at the last iterate */
+    double dual;            /* <phi, rho1 - rho0> at the last iterate */
+    double rel_gap;         /* (primal - dual) / primal, the precision measure of Sec. 8.1 */
+    double mass_residual;   /* ||div_x u + div_G w + rho1 - rho0|| / ||rho1 - rho0|| */
+    double R;               /* R^k itself */
+    int32_t converged;      /* 1 if residual <= tol at a check */
+    int32_t checks;         /* checks taken */
+} omt_info;
+
+typedef struct omt_ctx *omt_handle;
+typedef struct omt_bctx *omt_batch_handle;
+
+/* Fill *p with defaults: alpha 1, tau 1, rule step sizes, ||u||_{1,2},
+ * ||w||_1, FP32, no edges.  The caller still sets m, n, k and the graph. */
+void omt_params_init(omt_params *p);
+
+/* Host only (no device work).  Validate *p and report the resolved grid
+ * spacing and step sizes and lambda_max(-Delta_G) (Sec. 7.2).  Any output
+ * pointer may be NULL. */
+omt_status omt_resolve_params(const omt_params *p, double *h, double *mu, double *nu, double *lambda_max);
+
+/* Host only.  Bytes of device workspace omt_create needs for *p. */
+omt_status omt_workspace_bytes(const omt_params *p, size_t *bytes);
+
+/* Set up one problem.  rho0, rho1: device, m*n*k elements of p->dtype in the
+ * paper's layout; they are read during the call and not kept.  workspace:
+ * device, >= omt_workspace_bytes() bytes, 256-byte aligned, owned by the
+ * caller and kept until omt_destroy.  stream: hipStream_t (NULL = default).
+ * The call synchronises the stream once (mass check) and starts from
+ * u = w = phi = 0 (Sec. 7.2 leaves the initial guess open). */
+omt_status omt_create(const omt_params *p, const void *rho0, const void *rho1, void *workspace,
+                      size_t ws_bytes, void *stream, omt_handle *out);
+
+/* Run the method.  max_iters >= 0 iterations at most; tol > 0 stops at the
+ * first check with residual <= tol, tol <= 0 runs exactly max_iters.  Checks
+ * are taken every check_every iterations (<= 0: 64) and after the last one.
+ * Iterations continue from the current state.  info may be NULL.  Returns
+ * OMT_ENOTCONV when tol > 0 was not reached (outputs still valid). */
+omt_status omt_solve(omt_handle h, int64_t max_iters, double tol, int32_t check_every, omt_info *info);
+
+/* The transport cost V = ||u||_u + alpha ||w||_w of the current iterate
+ * (FP64 reduction; the discrete primal objective of App. A).  Also fills
+ * *info (nullable) with primal, dual, gap and mass residual of the iterate. */
+omt_status omt_distance(omt_handle h, double *V, omt_info *info);
+
+/* Gradients of V: d_rho0 = Phi, d_rho1 = -Phi (see the conventions above);
+ * device, m*n*k elements of the handle's dtype, paper layout.  Either may be
+ * NULL. */
+omt_status omt_grad(omt_handle h, void *d_rho0, void *d_rho1);
+
+/* Copy the state out / in (warm starts; the algorithm of Sec. 7.2 takes
+ * initial guesses).  Device, handle dtype, paper layout: phi m*n*k, u
+ * m*n*k*2 with the last index 0 for u_x and 1 for u_y, w m*n*l.  Any pointer
+ * may be NULL (that part is left alone; on set it is zeroed).  Ghost
+ * components (u_x on row m-1, u_y on column n-1, App. A) are zeroed on set. */
+omt_status omt_get_state(omt_handle h, void *phi, void *u, void *w);
+omt_status omt_set_state(omt_handle h, const void *phi, const void *u, const void *w);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+omt_status omt_destroy(omt_handle h);
+
+/* ------------------------------------------------------------- batched */
+
+/* Many independent problems of possibly different sizes, channel counts and
+ * graphs solved together: every iteration advances all unfinished pairs in
+ * one launch, and the launches of a check interval are replayed as one HIP
+ * graph.  params[b], rho0[b], rho1[b] as for omt_create (device pointers);
+ * one workspace of omt_batch_workspace_bytes(). */
+omt_status omt_batch_workspace_bytes(int32_t B, const omt_params *params, size_t *bytes);
+omt_status omt_batch_create(int32_t B, const omt_params *params, const void *const *rho0,
+                            const void *const *rho1, void *workspace, size_t ws_bytes, void *stream,
+                            omt_batch_handle *out);
+/* Each pair stops at its own first check with residual <= tol (checks every
+ * check_every iterations, as omt_solve); infos: host array of B (nullable). */
+omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, int32_t check_every,
+                           omt_info *infos);
+omt_status omt_batch_distance(omt_batch_handle h, double *V /* host, B */);
+omt_status omt_batch_grad(omt_batch_handle h, void *const *d_rho0, void *const *d_rho1);
+omt_status omt_batch_get_state(omt_batch_handle h, int32_t b, void *phi, void *u, void *w);
+omt_status omt_batch_destroy(omt_batch_handle h);
+
+/* ----------------------------------------------------------- utilities */
+
+/* Time the step kernel for each blocking depth T and rows-per-wave
+ * candidate on the handle's problem (state is saved and restored), verify
+ * that every candidate gives bit-identical iterates to T = 1, store the
+ * fastest in the handle and in the tuning cache (the JSON file named by
+ * OMT_TUNE_CACHE, if set).  best_t / best_rows / best_us (nullable) report
+ * the choice and its time per iteration in microseconds. */
+omt_status omt_autotune(omt_handle h, int32_t iters_per_trial, int32_t *best_t, int32_t *best_rows,
+                        double *best_us);
+
+/* Launch exactly n iterations of the step kernel with the given blocking
+ * depth (T must divide n) and report the mean time per launch in
+ * microseconds measured with HIP events on the handle's stream.  For
+ * measurement; the state advances by n iterations. */
+omt_status omt_time_steps(omt_handle h, int32_t T, int32_t rows_per_wave, int64_t n, double *us_per_launch);
+
+const char *omt_strerror(omt_status s);
+const char *omt_last_error(void);
+int32_t omt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OMT_H */

@@ -1,0 +1,330 @@
+// Set-up, reduction and layout kernels around the fused PDHG step: FP64
+// sums of the input densities (mass check), the source term f, the
+// per-check metrics (fixed-point residual of Sec. 6.1, primal and dual
+// objectives, constraint residual), the exported potential and the
+// conversions between the caller's layout (m x n x k, channel fastest) and
+// the SoA planes the step kernel streams.
+//
+// Every reduction writes one row of partial sums per workgroup (wavefront
+// shuffles, then LDS, in a fixed order) and a single-workgroup kernel sums
+// the rows in a fixed order, so results are deterministic.
+
+#include "omt_kernels.h"
+
+namespace omt {
+namespace {
+
+constexpr int RB = 256;  // threads per reduction workgroup
+
+template <typename R>
+__device__ __forceinline__ double ld(const void *p, int64_t i)
+{
+    return double(static_cast<const R *>(p)[i]);
+}
+
+__device__ __forceinline__ double ldv(const void *p, int dtype, int64_t i)
+{
+    return dtype == 1 ? ld<double>(p, i) : ld<float>(p, i);
+}
+
+__device__ __forceinline__ void stv(void *p, int dtype, int64_t i, double v)
+{
+    if (dtype == 1)
+        static_cast<double *>(p)[i] = v;
+    else
+        static_cast<float *>(p)[i] = float(v);
+}
+
+// Sum v[0..W) over the workgroup into out[0..W) (thread 0 writes).
+template <int W>
+__device__ void block_sum(double (&v)[W], double *out)
+{
+    __shared__ double sm[RB / WAVE][W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        double x = v[q];
+#pragma unroll
+        for (int off = WAVE / 2; off > 0; off >>= 1) x += __shfl_down(x, off, WAVE);
+        v[q] = x;
+    }
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) sm[wv][q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < RB / WAVE; ++w) s += sm[w][q];
+            out[q] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- set-up
+
+__global__ __launch_bounds__(RB) void sums_kernel(SumsArgs a)
+{
+    // channel by channel: sum rho0, sum rho1, sum |rho0|, sum |rho1|; the last
+    // column counts non-finite entries
+    const int W = 4 * a.k + 1;
+    double bad = 0.0;
+    for (int c = 0; c < a.k; ++c) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t p = blockIdx.x * (int64_t)RB + threadIdx.x; p < a.npix; p += (int64_t)a.nblocks * RB) {
+            const double x0 = ldv(a.rho0, a.dtype, p * a.k + c);
+            const double x1 = ldv(a.rho1, a.dtype, p * a.k + c);
+            if (!isfinite(x0) || !isfinite(x1)) {
+                bad += 1.0;
+                continue;
+            }
+            v[0] += x0;
+            v[1] += x1;
+            v[2] += fabs(x0);
+            v[3] += fabs(x1);
+        }
+        double o[4];
+        block_sum<4>(v, o);
+        if (threadIdx.x == 0) {
+            for (int q = 0; q < 4; ++q) a.partials[(int64_t)blockIdx.x * W + 4 * c + q] = o[q];
+        }
+    }
+    double b[1] = {bad};
+    double o1[1];
+    block_sum<1>(b, o1);
+    if (threadIdx.x == 0) a.partials[(int64_t)blockIdx.x * W + 4 * a.k] = o1[0];
+}
+
+__global__ void make_f_kernel(MakeFArgs a)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= (int64_t)a.m * a.n) return;
+    const int i = int(p / a.n), j = int(p % a.n);
+    for (int c = 0; c < a.k; ++c) {
+        const double x0 = ldv(a.rho0, a.dtype, p * a.k + c);
+        const double x1 = ldv(a.rho1, a.dtype, p * a.k + c);
+        stv(a.f, a.dtype, c * a.plane + (int64_t)i * a.pitch + j, (x1 - x0) - a.shift[c]);
+    }
+}
+
+// ---------------------------------------------------------------- metrics
+
+template <typename R>
+__global__ __launch_bounds__(RB) void metrics_kernel(MetricArgs a)
+{
+    const R *phi0 = static_cast<const R *>(a.phi0), *phi1 = static_cast<const R *>(a.phi1);
+    const R *u0 = static_cast<const R *>(a.u0), *u1 = static_cast<const R *>(a.u1);
+    const R *w0 = static_cast<const R *>(a.w0), *w1 = static_cast<const R *>(a.w1);
+    const R *f = static_cast<const R *>(a.f);
+    const int64_t P = a.plane;
+    const int k = a.k, l = a.l;
+    double v[NMET];
+#pragma unroll
+    for (int q = 0; q < NMET; ++q) v[q] = 0.0;
+
+    for (int64_t p = blockIdx.x * (int64_t)RB + threadIdx.x; p < (int64_t)a.m * a.n; p += (int64_t)a.nblocks * RB) {
+        const int i = int(p / a.n), j = int(p % a.n);
+        const int64_t o = (int64_t)i * a.pitch + j;
+        const int64_t oi = o - a.pitch, oj = o - 1;
+        double u2 = 0.0, w2 = 0.0;
+        for (int c = 0; c < k; ++c) {
+            double p0 = double(phi0[c * P + o]), p1 = double(phi1[c * P + o]);
+            if (a.plo0) {
+                p0 += double(a.plo0[c * P + o]);
+                p1 += double(a.plo1[c * P + o]);
+            }
+            const double dp = p1 - p0;
+            const double ux0 = i < a.m - 1 ? double(u0[c * P + o]) : 0.0;
+            const double ux1 = i < a.m - 1 ? double(u1[c * P + o]) : 0.0;
+            const double uy0 = j < a.n - 1 ? double(u0[(k + c) * P + o]) : 0.0;
+            const double uy1 = j < a.n - 1 ? double(u1[(k + c) * P + o]) : 0.0;
+            const double xl0 = i > 0 ? double(u0[c * P + oi]) : 0.0;
+            const double xl1 = i > 0 ? double(u1[c * P + oi]) : 0.0;
+            const double yl0 = j > 0 ? double(u0[(k + c) * P + oj]) : 0.0;
+            const double yl1 = j > 0 ? double(u1[(k + c) * P + oj]) : 0.0;
+            const double dux = ux1 - ux0, duy = uy1 - uy0;
+            const double ddiv = ((dux - (xl1 - xl0)) + duy - (yl1 - yl0)) * a.inv_h;
+            const double div1 = ((ux1 - xl1) + uy1 - yl1) * a.inv_h;
+            double dgd = 0.0, dg1 = 0.0;
+            for (int e = 0; e < l; ++e) {
+                const double we0 = double(w0[e * P + o]), we1 = double(w1[e * P + o]);
+                dgd += a.gm[c * LMAX + e] * (we1 - we0);
+                dg1 += a.gm[c * LMAX + e] * we1;
+            }
+            const double fc = double(f[c * P + o]);
+            v[0] += dux * dux + duy * duy;
+            v[2] += dp * dp;
+            v[3] += dp * (ddiv - dgd);
+            v[5] += p1 * fc;
+            const double r = (div1 - dg1) + fc;
+            v[6] += r * r;
+            v[7] += p1;
+            if (a.unorm == 0)
+                v[4] += sqrt(ux1 * ux1 + uy1 * uy1);
+            else if (a.unorm == 1)
+                v[4] += fabs(ux1) + fabs(uy1);
+            else
+                u2 += ux1 * ux1 + uy1 * uy1;
+        }
+        if (a.unorm == 2) v[4] += sqrt(u2);
+        double wn = 0.0;
+        for (int e = 0; e < l; ++e) {
+            const double we0 = double(w0[e * P + o]), we1 = double(w1[e * P + o]);
+            v[1] += (we1 - we0) * (we1 - we0);
+            if (a.wnorm == 0)
+                wn += fabs(we1);
+            else
+                w2 += we1 * we1;
+        }
+        if (a.wnorm == 1) wn = sqrt(w2);
+        v[4] += a.alpha * wn;
+    }
+    double out[NMET];
+    block_sum<NMET>(v, out);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < NMET; ++q) a.partials[(int64_t)blockIdx.x * NMET + q] = out[q];
+    }
+}
+
+__global__ __launch_bounds__(RB) void reduce_rows_kernel(const double *partials, int nblocks, int width, double *out)
+{
+    __shared__ double sm[RB];
+    for (int q = 0; q < width; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += RB) s += partials[(int64_t)b * width + q];
+        sm[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = RB / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[q] = sm[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(RB) void plane_sums_kernel(PlaneSumArgs a)
+{
+    for (int c = 0; c < a.k; ++c) {
+        double v[1] = {0.0};
+        for (int64_t p = blockIdx.x * (int64_t)RB + threadIdx.x; p < (int64_t)a.m * a.n; p += (int64_t)a.nblocks * RB) {
+            const int i = int(p / a.n), j = int(p % a.n);
+            const int64_t o = c * a.plane + (int64_t)i * a.pitch + j;
+            v[0] += ldv(a.phi, a.dtype, o) + (a.plo ? double(a.plo[o]) : 0.0);
+        }
+        double o1[1];
+        block_sum<1>(v, o1);
+        if (threadIdx.x == 0) a.partials[(int64_t)blockIdx.x * a.k + c] = o1[0];
+    }
+}
+
+__global__ void xfer_kernel(XferArgs a)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= (int64_t)a.m * a.n) return;
+    const int i = int(p / a.n), j = int(p % a.n);
+    const int64_t o = (int64_t)i * a.pitch + j;
+    const int k = a.k;
+    switch (a.mode) {
+        case 0:  // exported potential: sign * (-(phi - mean))
+            for (int c = 0; c < k; ++c) {
+                double x = ldv(a.src, a.dtype, c * a.plane + o);
+                if (a.plo) x += double(a.plo[c * a.plane + o]);
+                stv(a.dst, a.dtype, p * k + c, a.sign * (-(x - a.mean[c])));
+            }
+            break;
+        case 1:  // u planes -> m x n x k x 2
+            for (int c = 0; c < k; ++c) {
+                stv(a.dst, a.dtype, (p * k + c) * 2 + 0, ldv(a.src, a.dtype, c * a.plane + o));
+                stv(a.dst, a.dtype, (p * k + c) * 2 + 1, ldv(a.src, a.dtype, (k + c) * a.plane + o));
+            }
+            break;
+        case 2:  // planes -> m x n x k (w, or phi when plo is null)
+            for (int c = 0; c < k; ++c) {
+                double x = ldv(a.src, a.dtype, c * a.plane + o);
+                if (a.plo) x += double(a.plo[c * a.plane + o]);
+                stv(a.dst, a.dtype, p * k + c, x);
+            }
+            break;
+        case 3:  // m x n x k -> planes (phi or w); low parts cleared
+            for (int c = 0; c < k; ++c) {
+                stv(a.dst, a.dtype, c * a.plane + o, a.src ? ldv(a.src, a.dtype, p * k + c) : 0.0);
+                if (a.plo_out) a.plo_out[c * a.plane + o] = 0.0f;
+            }
+            break;
+        case 4:  // m x n x k x 2 -> u planes, ghosts zeroed (App. A)
+            for (int c = 0; c < k; ++c) {
+                const double x = (a.src && i < a.m - 1) ? ldv(a.src, a.dtype, (p * k + c) * 2 + 0) : 0.0;
+                const double y = (a.src && j < a.n - 1) ? ldv(a.src, a.dtype, (p * k + c) * 2 + 1) : 0.0;
+                stv(a.dst, a.dtype, c * a.plane + o, x);
+                stv(a.dst, a.dtype, (k + c) * a.plane + o, y);
+            }
+            break;
+        default:
+            break;
+    }
+}
+
+__global__ void zero_kernel(uint32_t *p, int64_t n)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = 0u;
+}
+
+}  // namespace
+
+hipError_t launch_sums(const SumsArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(sums_kernel, dim3(a.nblocks), dim3(RB), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_f(const MakeFArgs &a, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.m * a.n;
+    hipLaunchKernelGGL(make_f_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_metrics(const MetricArgs &a, hipStream_t s)
+{
+    if (a.dtype == 1)
+        hipLaunchKernelGGL(metrics_kernel<double>, dim3(a.nblocks), dim3(RB), 0, s, a);
+    else
+        hipLaunchKernelGGL(metrics_kernel<float>, dim3(a.nblocks), dim3(RB), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_rows(const double *partials, int nblocks, int width, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(RB), 0, s, partials, nblocks, width, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_sums(const PlaneSumArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(plane_sums_kernel, dim3(a.nblocks), dim3(RB), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_xfer(const XferArgs &a, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.m * a.n;
+    hipLaunchKernelGGL(xfer_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const int64_t n = int64_t(bytes / 4);
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(zero_kernel, dim3(unsigned(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s,
+                       static_cast<uint32_t *>(p), n);
+    return hipGetLastError();
+}
+
+}  // namespace omt

@@ -1,0 +1,887 @@
+// Host driver and C ABI (include/omt.h) of the vector-OMT solver.
+//
+// Parameter validation, the step sizes of Sec. 7.2 (lambda_max(-Delta_G) by
+// cyclic Jacobi on the k x k graph Laplacian of Sec. 3.1), the mass check,
+// workspace layout, the iteration loop with its check cadence, and the
+// stopping rule on the fixed-point residual R^k of Sec. 6.1.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/omt.h"
+#include "omt_kernels.h"
+
+namespace omt {
+
+hipError_t launch_step_k1(const StepLaunch &);
+hipError_t launch_step_k2(const StepLaunch &);
+hipError_t launch_step_k3(const StepLaunch &);
+hipError_t launch_step_k4(const StepLaunch &);
+hipError_t launch_step_k5(const StepLaunch &);
+hipError_t launch_step_k6(const StepLaunch &);
+hipError_t launch_step_k7(const StepLaunch &);
+hipError_t launch_step_k8(const StepLaunch &);
+bool step_supported_k1(int, int, int, bool);
+bool step_supported_k2(int, int, int, bool);
+bool step_supported_k3(int, int, int, bool);
+bool step_supported_k4(int, int, int, bool);
+bool step_supported_k5(int, int, int, bool);
+bool step_supported_k6(int, int, int, bool);
+bool step_supported_k7(int, int, int, bool);
+bool step_supported_k8(int, int, int, bool);
+
+hipError_t launch_step(const StepLaunch &L)
+{
+    switch (L.k) {
+        case 1: return launch_step_k1(L);
+        case 2: return launch_step_k2(L);
+        case 3: return launch_step_k3(L);
+        case 4: return launch_step_k4(L);
+        case 5: return launch_step_k5(L);
+        case 6: return launch_step_k6(L);
+        case 7: return launch_step_k7(L);
+        case 8: return launch_step_k8(L);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool step_supported(int dtype, int k, int lb, int T, bool comp)
+{
+    switch (k) {
+        case 1: return step_supported_k1(dtype, lb, T, comp);
+        case 2: return step_supported_k2(dtype, lb, T, comp);
+        case 3: return step_supported_k3(dtype, lb, T, comp);
+        case 4: return step_supported_k4(dtype, lb, T, comp);
+        case 5: return step_supported_k5(dtype, lb, T, comp);
+        case 6: return step_supported_k6(dtype, lb, T, comp);
+        case 7: return step_supported_k7(dtype, lb, T, comp);
+        case 8: return step_supported_k8(dtype, lb, T, comp);
+        default: return false;
+    }
+}
+
+}  // namespace omt
+
+using namespace omt;
+
+// ------------------------------------------------------------------ errors
+
+namespace {
+
+thread_local std::string g_last_error;
+
+omt_status fail(omt_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) return fail(OMT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+// ------------------------------------------------------------------ graph
+
+// Largest eigenvalue of a symmetric matrix by the cyclic Jacobi method.
+double jacobi_lambda_max(std::vector<double> A, int k)
+{
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int p = 0; p < k; ++p)
+            for (int q = 0; q < k; ++q) {
+                tot += A[p * k + q] * A[p * k + q];
+                if (p != q) off += A[p * k + q] * A[p * k + q];
+            }
+        if (off <= 1e-30 * std::max(tot, 1e-300)) break;
+        for (int p = 0; p + 1 < k; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                const double apq = A[p * k + q];
+                if (apq == 0.0) continue;
+                const double th = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int r = 0; r < k; ++r) {
+                    const double a = A[r * k + p], b = A[r * k + q];
+                    A[r * k + p] = cs * a - sn * b;
+                    A[r * k + q] = sn * a + cs * b;
+                }
+                for (int r = 0; r < k; ++r) {
+                    const double a = A[p * k + r], b = A[q * k + r];
+                    A[p * k + r] = cs * a - sn * b;
+                    A[q * k + r] = sn * a + cs * b;
+                }
+            }
+    }
+    double mx = 0.0;
+    for (int p = 0; p < k; ++p) mx = std::max(mx, A[p * k + p]);
+    return mx;
+}
+
+struct Resolved {
+    int m, n, k, l, lb;
+    std::vector<int32_t> edges;
+    std::vector<double> cost;
+    double alpha, tau, mu, nu, h, lmax;
+    int unorm, wnorm, dtype;
+    bool comp;
+    int tblock, rows;
+    std::vector<int> cls;  // mass class per channel
+    int ncls;
+};
+
+omt_status resolve(const omt_params *p, Resolved &r)
+{
+    if (!p) return fail(OMT_EINVAL, "params is NULL");
+    if (p->m < 2 || p->n < 2) return fail(OMT_EINVAL, "grid must be at least 2 x 2 (got %d x %d)", p->m, p->n);
+    if ((int64_t)p->m * p->n > (int64_t)1 << 31) return fail(OMT_EINVAL, "grid too large");
+    if (p->k < 1) return fail(OMT_EINVAL, "k must be >= 1 (got %d)", p->k);
+    if (p->k > OMT_MAX_CHANNELS) return fail(OMT_EUNSUPPORTED, "k = %d exceeds %d", p->k, OMT_MAX_CHANNELS);
+    if (p->n_edges < 0) return fail(OMT_EGRAPH, "negative edge count");
+    if (p->n_edges > 0 && !p->edges) return fail(OMT_EGRAPH, "edges is NULL");
+    if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(OMT_EINVAL, "alpha must be > 0");
+    if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(OMT_EINVAL, "tau must be > 0");
+    if (p->mu < 0.0 || p->nu < 0.0 || p->h < 0.0 || !std::isfinite(p->mu) || !std::isfinite(p->nu) ||
+        !std::isfinite(p->h))
+        return fail(OMT_EINVAL, "mu, nu, h must be finite and >= 0");
+    if (p->unorm < 0 || p->unorm > 2) return fail(OMT_EINVAL, "unknown u norm %d", p->unorm);
+    if (p->wnorm < 0 || p->wnorm > 1) return fail(OMT_EINVAL, "unknown w norm %d", p->wnorm);
+    if (p->dtype != OMT_F32 && p->dtype != OMT_F64) return fail(OMT_EINVAL, "unknown dtype %d", p->dtype);
+    if (p->tblock < 0 || p->rows_per_wave < 0) return fail(OMT_EINVAL, "tblock and rows_per_wave must be >= 0");
+
+    r.m = p->m;
+    r.n = p->n;
+    r.k = p->k;
+    r.l = p->n_edges;
+    r.edges.assign(p->edges, p->edges + 2 * r.l);
+    r.cost.assign(r.l, 1.0);
+    if (p->edge_cost)
+        for (int e = 0; e < r.l; ++e) r.cost[e] = p->edge_cost[e];
+    for (int e = 0; e < r.l; ++e) {
+        const int a = r.edges[2 * e], b = r.edges[2 * e + 1];
+        if (a < 0 || b >= r.k || a >= b)
+            return fail(OMT_EGRAPH, "edge %d = (%d, %d): need 0 <= a < b < k = %d", e, a, b, r.k);
+        if (!(r.cost[e] > 0.0) || !std::isfinite(r.cost[e]))
+            return fail(OMT_EGRAPH, "edge %d has cost %g, need > 0", e, r.cost[e]);
+        for (int f = 0; f < e; ++f)
+            if (r.edges[2 * f] == a && r.edges[2 * f + 1] == b) return fail(OMT_EGRAPH, "duplicate edge (%d, %d)", a, b);
+    }
+    if (r.l > LMAX) return fail(OMT_EUNSUPPORTED, "%d edges exceed %d", r.l, LMAX);
+    r.lb = edge_bucket(r.k, r.l);
+    r.alpha = p->alpha;
+    r.tau = p->tau;
+    r.unorm = p->unorm;
+    r.wnorm = p->wnorm;
+    r.dtype = p->dtype;
+    r.comp = (p->flags & OMT_FLAG_COMPENSATED_PHI) && p->dtype == OMT_F32;
+    r.tblock = p->tblock;
+    r.rows = p->rows_per_wave;
+    r.h = p->h > 0.0 ? p->h : 1.0 / double(std::max(r.m, r.n) - 1);
+
+    // lambda_max(-Delta_G), -Delta_G = D diag(1/c^2) D^T (Sec. 3.1)
+    r.lmax = 0.0;
+    if (r.l > 0) {
+        std::vector<double> A(r.k * r.k, 0.0);
+        for (int e = 0; e < r.l; ++e) {
+            const int a = r.edges[2 * e], b = r.edges[2 * e + 1];
+            const double wgt = 1.0 / (r.cost[e] * r.cost[e]);
+            A[a * r.k + a] += wgt;
+            A[b * r.k + b] += wgt;
+            A[a * r.k + b] -= wgt;
+            A[b * r.k + a] -= wgt;
+        }
+        r.lmax = jacobi_lambda_max(A, r.k);
+    }
+    // step sizes of Sec. 7.1 / 7.2 unless given
+    const double h2 = r.h * r.h;
+    r.mu = p->mu > 0.0 ? p->mu : (r.l == 0 ? h2 / (16.0 * r.tau) : h2 / (32.0 * r.tau));
+    r.nu = r.l == 0 ? 0.0 : (p->nu > 0.0 ? p->nu : 1.0 / (4.0 * r.tau * r.lmax));
+    if (p->mu > 0.0 || p->nu > 0.0) {
+        const double cond = r.tau * r.mu * 8.0 / h2 + r.tau * r.nu * r.lmax;
+        if (!(cond < 1.0))
+            return fail(OMT_ESTEP, "tau mu 8/h^2 + tau nu lambda_max = %g must be < 1 (Sec. 7.2)", cond);
+    }
+    // mass classes: connected components of the channel graph
+    r.cls.resize(r.k);
+    for (int c = 0; c < r.k; ++c) r.cls[c] = c;
+    for (bool ch = true; ch;) {
+        ch = false;
+        for (int e = 0; e < r.l; ++e) {
+            int &a = r.cls[r.edges[2 * e]], &b = r.cls[r.edges[2 * e + 1]];
+            const int lo = std::min(a, b);
+            if (a != lo || b != lo) {
+                a = b = lo;
+                ch = true;
+            }
+        }
+    }
+    std::vector<int> map(r.k, -1);
+    r.ncls = 0;
+    for (int c = 0; c < r.k; ++c) {
+        if (map[r.cls[c]] < 0) map[r.cls[c]] = r.ncls++;
+        r.cls[c] = map[r.cls[c]];
+    }
+    return OMT_OK;
+}
+
+// ------------------------------------------------------------------ layout
+
+constexpr int METRIC_BLOCKS_MAX = 1024;
+constexpr int SUM_BLOCKS_MAX = 512;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    int pitch;
+    int64_t plane;  // elements
+    size_t esz;
+    size_t off_f, off_phi[2], off_u[2], off_w[2], off_plo[2], off_part, off_res, off_vec, total;
+};
+
+Layout make_layout(const Resolved &r)
+{
+    Layout L;
+    L.esz = r.dtype == OMT_F64 ? 8 : 4;
+    L.pitch = (r.n + 63) / 64 * 64;
+    L.plane = (int64_t)r.m * L.pitch;
+    const size_t pb = align256(size_t(L.plane) * L.esz);
+    size_t o = 0;
+    L.off_f = o;
+    o += pb * r.k;
+    for (int b = 0; b < 2; ++b) {
+        L.off_phi[b] = o;
+        o += pb * r.k;
+    }
+    for (int b = 0; b < 2; ++b) {
+        L.off_u[b] = o;
+        o += pb * 2 * r.k;
+    }
+    for (int b = 0; b < 2; ++b) {
+        L.off_w[b] = o;
+        o += pb * r.l;
+    }
+    const size_t pf = align256(size_t(L.plane) * 4);
+    for (int b = 0; b < 2; ++b) {
+        L.off_plo[b] = o;
+        o += r.comp ? pf * r.k : 0;
+    }
+    L.off_part = o;
+    o += align256(sizeof(double) * size_t(std::max(METRIC_BLOCKS_MAX * NMET, SUM_BLOCKS_MAX * (4 * KMAX + 1))));
+    L.off_res = o;
+    o += align256(sizeof(double) * 64);
+    L.off_vec = o;
+    o += align256(sizeof(double) * 64);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+
+struct omt_ctx {
+    Resolved r;
+    Layout L;
+    hipStream_t stream;
+    int device;
+    char *ws;
+    void *f, *phi[2], *u[2], *w[2];
+    float *plo[2];
+    double *part, *res, *vec;
+    double *host;  // pinned, 64 doubles
+    int cur, wcur;
+    double fnorm2;
+    int metric_blocks;
+    int64_t iters_done;
+    omt_info last;
+    bool have_last;
+};
+
+namespace {
+
+template <typename R>
+void fill_step_args(StepArgs<R> &a, const omt_ctx *h, int T, int rows, bool w_inplace, int ncolw, int nroww,
+                    int nwg)
+{
+    const Resolved &r = h->r;
+    const int nc = h->cur, nx = 1 - h->cur;
+    a.phi_in = static_cast<const R *>(h->phi[nc]);
+    a.phi_out = static_cast<R *>(h->phi[nx]);
+    a.u_in = static_cast<const R *>(h->u[nc]);
+    a.u_out = static_cast<R *>(h->u[nx]);
+    a.w_in = static_cast<const R *>(h->w[h->wcur]);
+    a.w_out = static_cast<R *>(h->w[w_inplace ? h->wcur : 1 - h->wcur]);
+    a.f = static_cast<const R *>(h->f);
+    a.plo_in = r.comp ? h->plo[nc] : nullptr;
+    a.plo_out = r.comp ? h->plo[nx] : nullptr;
+    a.plane = h->L.plane;
+    a.m = r.m;
+    a.n = r.n;
+    a.pitch = h->L.pitch;
+    a.l = r.l;
+    a.unorm = r.unorm;
+    a.wnorm = r.wnorm;
+    a.rows = rows;
+    a.ncolw = ncolw;
+    a.nroww = nroww;
+    a.nwg = nwg;
+    a.mu = R(r.mu);
+    a.mu_h = R(r.mu / r.h);
+    a.nu = R(r.nu);
+    a.anu = R(r.alpha * r.nu);
+    a.tau = R(r.tau);
+    a.inv_h = R(1.0 / r.h);
+    for (int q = 0; q < KMAX * LMAX; ++q) a.gm[q] = R(0);
+    for (int e = 0; e < r.l; ++e) {
+        a.gm[r.edges[2 * e] * LMAX + e] = R(1.0 / r.cost[e]);
+        a.gm[r.edges[2 * e + 1] * LMAX + e] = R(-1.0 / r.cost[e]);
+    }
+}
+
+int default_rows(const omt_ctx *h, int T)
+{
+    if (h->r.rows > 0) return h->r.rows;
+    // enough waves to cover the chip (>= ~2 per SIMD), chunks of 4..32 rows
+    const int ncolw = (h->r.n + (WAVE - 2 * T) - 1) / (WAVE - 2 * T);
+    const int want_waves = 2048;
+    int rows = int((int64_t)h->r.m * ncolw / want_waves);
+    rows = std::max(rows, 4 * T);
+    rows = std::min(rows, 32);
+    return std::max(rows, 1);
+}
+
+// One launch advancing T iterations.  w is updated in place when allowed.
+omt_status step_launch(omt_ctx *h, int T, int rows, bool w_inplace)
+{
+    const Resolved &r = h->r;
+    if (!step_supported(r.dtype, r.k, r.lb, T, r.comp))
+        return fail(OMT_EUNSUPPORTED, "no step kernel for dtype %d, k %d, edge bucket %d, T %d", r.dtype, r.k, r.lb, T);
+    if (T > 1) w_inplace = false;  // halo lanes of a pipelined step must see the old w
+    const int ncolw = (r.n + (WAVE - 2 * T) - 1) / (WAVE - 2 * T);
+    const int nroww = (r.m + rows - 1) / rows;
+    const int nwg = ncolw * ((nroww + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG);
+    StepLaunch Lc;
+    Lc.dtype = r.dtype;
+    Lc.k = r.k;
+    Lc.lb = r.lb;
+    Lc.T = T;
+    Lc.comp = r.comp;
+    Lc.stream = h->stream;
+    hipError_t e;
+    if (r.dtype == OMT_F64) {
+        StepArgs<double> a;
+        fill_step_args(a, h, T, rows, w_inplace, ncolw, nroww, nwg);
+        Lc.args = &a;
+        e = launch_step(Lc);
+    } else {
+        StepArgs<float> a;
+        fill_step_args(a, h, T, rows, w_inplace, ncolw, nroww, nwg);
+        Lc.args = &a;
+        e = launch_step(Lc);
+    }
+    if (e != hipSuccess) return fail(OMT_EDEVICE, "step launch: %s", hipGetErrorString(e));
+    h->cur = 1 - h->cur;
+    if (!w_inplace) h->wcur = 1 - h->wcur;
+    h->iters_done += T;
+    return OMT_OK;
+}
+
+// Metrics of (old -> new) state buffers; results into h->res[0..NMET).
+omt_status run_metrics(omt_ctx *h, int old_c, int new_c, int old_w, int new_w)
+{
+    const Resolved &r = h->r;
+    MetricArgs a;
+    a.phi0 = h->phi[old_c];
+    a.phi1 = h->phi[new_c];
+    a.u0 = h->u[old_c];
+    a.u1 = h->u[new_c];
+    a.w0 = h->w[old_w];
+    a.w1 = h->w[new_w];
+    a.f = h->f;
+    a.plo0 = r.comp ? h->plo[old_c] : nullptr;
+    a.plo1 = r.comp ? h->plo[new_c] : nullptr;
+    a.dtype = r.dtype;
+    a.m = r.m;
+    a.n = r.n;
+    a.k = r.k;
+    a.l = r.l;
+    a.pitch = h->L.pitch;
+    a.plane = h->L.plane;
+    a.unorm = r.unorm;
+    a.wnorm = r.wnorm;
+    a.inv_h = 1.0 / r.h;
+    a.alpha = r.alpha;
+    for (int q = 0; q < KMAX * LMAX; ++q) a.gm[q] = 0.0;
+    for (int e = 0; e < r.l; ++e) {
+        a.gm[r.edges[2 * e] * LMAX + e] = 1.0 / r.cost[e];
+        a.gm[r.edges[2 * e + 1] * LMAX + e] = -1.0 / r.cost[e];
+    }
+    a.partials = h->part;
+    a.nblocks = h->metric_blocks;
+    HIP_TRY(launch_metrics(a, h->stream));
+    HIP_TRY(launch_reduce_rows(h->part, a.nblocks, NMET, h->res, h->stream));
+    return OMT_OK;
+}
+
+omt_status read_results(omt_ctx *h, int count)
+{
+    HIP_TRY(hipMemcpyAsync(h->host, h->res, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return OMT_OK;
+}
+
+void fill_info(omt_ctx *h, const double *met, omt_info *info)
+{
+    const Resolved &r = h->r;
+    const double R = met[0] / r.mu + (r.l > 0 ? met[1] / r.nu : 0.0) + met[2] / r.tau - 2.0 * met[3];
+    const double R0 = r.tau * h->fnorm2;
+    info->R = R;
+    info->residual = R0 > 0.0 ? std::sqrt(std::max(R, 0.0) / R0) : 0.0;
+    if (!std::isfinite(R)) info->residual = R;
+    info->primal = met[4];
+    info->dual = met[5];
+    info->rel_gap = met[4] > 0.0 ? (met[4] - met[5]) / met[4] : 0.0;
+    info->mass_residual = h->fnorm2 > 0.0 ? std::sqrt(met[6] / h->fnorm2) : 0.0;
+}
+
+int tblock_of(const omt_ctx *h)
+{
+    if (h->r.tblock > 0) return h->r.tblock;
+    return 1;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+void omt_params_init(omt_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->alpha = 1.0;
+    p->tau = 1.0;
+    p->unorm = OMT_U_L12;
+    p->wnorm = OMT_W_L1;
+    p->dtype = OMT_F32;
+}
+
+omt_status omt_resolve_params(const omt_params *p, double *h, double *mu, double *nu, double *lambda_max)
+{
+    Resolved r;
+    omt_status s = resolve(p, r);
+    if (s != OMT_OK) return s;
+    if (h) *h = r.h;
+    if (mu) *mu = r.mu;
+    if (nu) *nu = r.nu;
+    if (lambda_max) *lambda_max = r.lmax;
+    return OMT_OK;
+}
+
+omt_status omt_workspace_bytes(const omt_params *p, size_t *bytes)
+{
+    if (!bytes) return fail(OMT_EINVAL, "bytes is NULL");
+    Resolved r;
+    omt_status s = resolve(p, r);
+    if (s != OMT_OK) return s;
+    *bytes = make_layout(r).total;
+    return OMT_OK;
+}
+
+omt_status omt_create(const omt_params *p, const void *rho0, const void *rho1, void *workspace, size_t ws_bytes,
+                      void *stream, omt_handle *out)
+{
+    if (!out) return fail(OMT_EINVAL, "out is NULL");
+    *out = nullptr;
+    Resolved r;
+    omt_status s = resolve(p, r);
+    if (s != OMT_OK) return s;
+    if (!rho0 || !rho1) return fail(OMT_EINVAL, "rho0 / rho1 is NULL");
+    if (!workspace) return fail(OMT_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(OMT_EINVAL, "workspace not 256-byte aligned");
+    const Layout L = make_layout(r);
+    if (ws_bytes < L.total) return fail(OMT_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
+
+    omt_ctx *h = new omt_ctx();
+    h->r = r;
+    h->L = L;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->ws = static_cast<char *>(workspace);
+    h->f = h->ws + L.off_f;
+    for (int b = 0; b < 2; ++b) {
+        h->phi[b] = h->ws + L.off_phi[b];
+        h->u[b] = h->ws + L.off_u[b];
+        h->w[b] = h->ws + L.off_w[b];
+        h->plo[b] = r.comp ? reinterpret_cast<float *>(h->ws + L.off_plo[b]) : nullptr;
+    }
+    h->part = reinterpret_cast<double *>(h->ws + L.off_part);
+    h->res = reinterpret_cast<double *>(h->ws + L.off_res);
+    h->vec = reinterpret_cast<double *>(h->ws + L.off_vec);
+    h->cur = h->wcur = 0;
+    h->iters_done = 0;
+    h->have_last = false;
+    const int64_t npix = (int64_t)r.m * r.n;
+    h->metric_blocks = int(std::min<int64_t>(METRIC_BLOCKS_MAX, (npix + 255) / 256));
+    auto bail = [&](omt_status st) {
+        if (h->host) (void)hipHostFree(h->host);
+        delete h;
+        return st;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&h->host), sizeof(double) * 64, hipHostMallocDefault);
+    if (e != hipSuccess) return bail(fail(OMT_EDEVICE, "set-up: %s", hipGetErrorString(e)));
+
+    // FP64 per-channel masses and non-finite count of the inputs
+    SumsArgs sa;
+    sa.rho0 = rho0;
+    sa.rho1 = rho1;
+    sa.dtype = r.dtype;
+    sa.npix = npix;
+    sa.k = r.k;
+    sa.partials = h->part;
+    sa.nblocks = int(std::min<int64_t>(SUM_BLOCKS_MAX, (npix + 255) / 256));
+    const int W = 4 * r.k + 1;
+    e = launch_sums(sa, h->stream);
+    if (e == hipSuccess) e = launch_reduce_rows(h->part, sa.nblocks, W, h->res, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->host, h->res, sizeof(double) * W, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return bail(fail(OMT_EDEVICE, "mass check: %s", hipGetErrorString(e)));
+    std::vector<double> sums(h->host, h->host + W);
+    if (sums[4 * r.k] > 0.0) return bail(fail(OMT_EINVAL, "%.0f non-finite input values", sums[4 * r.k]));
+    std::vector<double> s0(r.ncls, 0.0), s1(r.ncls, 0.0), a0(r.ncls, 0.0), a1(r.ncls, 0.0), cnt(r.ncls, 0.0);
+    for (int c = 0; c < r.k; ++c) {
+        const int g = r.cls[c];
+        s0[g] += sums[4 * c];
+        s1[g] += sums[4 * c + 1];
+        a0[g] += sums[4 * c + 2];
+        a1[g] += sums[4 * c + 3];
+        cnt[g] += double(npix);
+    }
+    for (int g = 0; g < r.ncls; ++g) {
+        const double den = std::max(a0[g], a1[g]);
+        const double rel = den > 0.0 ? std::fabs(s0[g] - s1[g]) / den : 0.0;
+        if (rel > 1e-6)
+            return bail(fail(OMT_EMASS, "mass class %d: sum rho0 = %.9g, sum rho1 = %.9g (relative %.3g > 1e-6)", g,
+                             s0[g], s1[g], rel));
+    }
+    for (int c = 0; c < r.k; ++c) h->host[c] = (s1[r.cls[c]] - s0[r.cls[c]]) / cnt[r.cls[c]];
+    e = hipMemcpyAsync(h->vec, h->host, sizeof(double) * r.k, hipMemcpyHostToDevice, h->stream);
+    // f = rho1 - rho0 - class mean, state = 0
+    MakeFArgs fa;
+    fa.rho0 = rho0;
+    fa.rho1 = rho1;
+    fa.dtype = r.dtype;
+    fa.m = r.m;
+    fa.n = r.n;
+    fa.k = r.k;
+    fa.pitch = L.pitch;
+    fa.plane = L.plane;
+    fa.shift = h->vec;
+    fa.f = h->f;
+    if (e == hipSuccess) e = launch_zero(h->ws, L.off_part, h->stream);
+    if (e == hipSuccess) e = launch_make_f(fa, h->stream);
+    if (e != hipSuccess) return bail(fail(OMT_EDEVICE, "set-up: %s", hipGetErrorString(e)));
+    // ||f||^2 from the objectives of the zero state
+    s = run_metrics(h, 0, 0, 0, 0);
+    if (s == OMT_OK) s = read_results(h, NMET);
+    if (s != OMT_OK) return bail(s);
+    h->fnorm2 = h->host[6];
+    *out = h;
+    return OMT_OK;
+}
+
+omt_status omt_solve(omt_handle h, int64_t max_iters, double tol, int32_t check_every, omt_info *info)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    if (max_iters < 0) return fail(OMT_EINVAL, "max_iters < 0");
+    const int K = check_every > 0 ? check_every : 64;
+    const int T = tblock_of(h);
+    omt_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    omt_status s = OMT_OK;
+    int64_t it = 0;
+    while (it < max_iters) {
+        const int64_t nblk = std::min<int64_t>(K, max_iters - it);
+        // nblk - 1 iterations, T per launch while T fits, then single steps
+        int64_t rest = nblk - 1;
+        const int rowsT = default_rows(h, T);
+        while (T > 1 && rest >= T) {
+            if ((s = step_launch(h, T, rowsT, false)) != OMT_OK) return s;
+            rest -= T;
+        }
+        const int rows1 = default_rows(h, 1);
+        while (rest > 0) {
+            if ((s = step_launch(h, 1, rows1, true)) != OMT_OK) return s;
+            --rest;
+        }
+        // the checked iteration keeps both iterates for R^k
+        const int oc = h->cur, ow = h->wcur;
+        if ((s = step_launch(h, 1, rows1, false)) != OMT_OK) return s;
+        if ((s = run_metrics(h, oc, h->cur, ow, h->wcur)) != OMT_OK) return s;
+        if ((s = read_results(h, NMET)) != OMT_OK) return s;
+        it += nblk;
+        fill_info(h, h->host, &inf);
+        inf.iters = it;
+        inf.checks += 1;
+        if (!std::isfinite(inf.R) || !std::isfinite(inf.primal)) {
+            h->last = inf;
+            h->have_last = true;
+            if (info) *info = inf;
+            return fail(OMT_EDIVERGED, "non-finite residual after %lld iterations", (long long)it);
+        }
+        if (tol > 0.0 && inf.residual <= tol) {
+            inf.converged = 1;
+            break;
+        }
+    }
+    h->last = inf;
+    h->have_last = true;
+    if (info) *info = inf;
+    if (tol > 0.0 && !inf.converged) return fail(OMT_ENOTCONV, "residual %.3g > tol %.3g after %lld iterations",
+                                                  inf.residual, tol, (long long)it);
+    return OMT_OK;
+}
+
+omt_status omt_distance(omt_handle h, double *V, omt_info *info)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    omt_status s = run_metrics(h, h->cur, h->cur, h->wcur, h->wcur);
+    if (s == OMT_OK) s = read_results(h, NMET);
+    if (s != OMT_OK) return s;
+    omt_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    fill_info(h, h->host, &inf);
+    if (h->have_last) {
+        inf.iters = h->last.iters;
+        inf.residual = h->last.residual;
+        inf.R = h->last.R;
+        inf.converged = h->last.converged;
+        inf.checks = h->last.checks;
+    }
+    if (V) *V = inf.primal;
+    if (info) *info = inf;
+    return OMT_OK;
+}
+
+omt_status omt_grad(omt_handle h, void *d_rho0, void *d_rho1)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    const Resolved &r = h->r;
+    PlaneSumArgs pa;
+    pa.phi = h->phi[h->cur];
+    pa.plo = r.comp ? h->plo[h->cur] : nullptr;
+    pa.dtype = r.dtype;
+    pa.m = r.m;
+    pa.n = r.n;
+    pa.k = r.k;
+    pa.pitch = h->L.pitch;
+    pa.plane = h->L.plane;
+    pa.partials = h->part;
+    pa.nblocks = h->metric_blocks;
+    HIP_TRY(launch_plane_sums(pa, h->stream));
+    HIP_TRY(launch_reduce_rows(h->part, pa.nblocks, r.k, h->res, h->stream));
+    omt_status s = read_results(h, r.k);
+    if (s != OMT_OK) return s;
+    std::vector<double> cs(r.ncls, 0.0), cn(r.ncls, 0.0);
+    for (int c = 0; c < r.k; ++c) {
+        cs[r.cls[c]] += h->host[c];
+        cn[r.cls[c]] += double(r.m) * r.n;
+    }
+    for (int c = 0; c < r.k; ++c) h->host[c] = cs[r.cls[c]] / cn[r.cls[c]];
+    HIP_TRY(hipMemcpyAsync(h->vec, h->host, sizeof(double) * r.k, hipMemcpyHostToDevice, h->stream));
+    XferArgs xa;
+    xa.src = h->phi[h->cur];
+    xa.plo = pa.plo;
+    xa.plo_out = nullptr;
+    xa.dtype = r.dtype;
+    xa.m = r.m;
+    xa.n = r.n;
+    xa.k = r.k;
+    xa.pitch = h->L.pitch;
+    xa.plane = h->L.plane;
+    xa.mode = 0;
+    xa.mean = h->vec;
+    if (d_rho0) {
+        xa.dst = d_rho0;
+        xa.sign = 1.0;
+        HIP_TRY(launch_xfer(xa, h->stream));
+    }
+    if (d_rho1) {
+        xa.dst = d_rho1;
+        xa.sign = -1.0;
+        HIP_TRY(launch_xfer(xa, h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return OMT_OK;
+}
+
+omt_status omt_get_state(omt_handle h, void *phi, void *u, void *w)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    const Resolved &r = h->r;
+    XferArgs xa;
+    std::memset(&xa, 0, sizeof(xa));
+    xa.dtype = r.dtype;
+    xa.m = r.m;
+    xa.n = r.n;
+    xa.pitch = h->L.pitch;
+    xa.plane = h->L.plane;
+    if (phi) {
+        xa.src = h->phi[h->cur];
+        xa.plo = r.comp ? h->plo[h->cur] : nullptr;
+        xa.dst = phi;
+        xa.k = r.k;
+        xa.mode = 2;
+        HIP_TRY(launch_xfer(xa, h->stream));
+    }
+    if (u) {
+        xa.src = h->u[h->cur];
+        xa.plo = nullptr;
+        xa.dst = u;
+        xa.k = r.k;
+        xa.mode = 1;
+        HIP_TRY(launch_xfer(xa, h->stream));
+    }
+    if (w && r.l > 0) {
+        xa.src = h->w[h->wcur];
+        xa.plo = nullptr;
+        xa.dst = w;
+        xa.k = r.l;
+        xa.mode = 2;
+        HIP_TRY(launch_xfer(xa, h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return OMT_OK;
+}
+
+omt_status omt_set_state(omt_handle h, const void *phi, const void *u, const void *w)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    const Resolved &r = h->r;
+    XferArgs xa;
+    std::memset(&xa, 0, sizeof(xa));
+    xa.dtype = r.dtype;
+    xa.m = r.m;
+    xa.n = r.n;
+    xa.pitch = h->L.pitch;
+    xa.plane = h->L.plane;
+    xa.src = phi;
+    xa.dst = h->phi[h->cur];
+    xa.plo_out = r.comp ? h->plo[h->cur] : nullptr;
+    xa.k = r.k;
+    xa.mode = 3;
+    HIP_TRY(launch_xfer(xa, h->stream));
+    xa.src = u;
+    xa.dst = h->u[h->cur];
+    xa.plo_out = nullptr;
+    xa.mode = 4;
+    HIP_TRY(launch_xfer(xa, h->stream));
+    if (r.l > 0) {
+        xa.src = w;
+        xa.dst = h->w[h->wcur];
+        xa.k = r.l;
+        xa.mode = 3;
+        HIP_TRY(launch_xfer(xa, h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->have_last = false;
+    return OMT_OK;
+}
+
+omt_status omt_destroy(omt_handle h)
+{
+    if (!h) return OMT_OK;
+    if (h->host) (void)hipHostFree(h->host);
+    delete h;
+    return OMT_OK;
+}
+
+omt_status omt_time_steps(omt_handle h, int32_t T, int32_t rows_per_wave, int64_t n, double *us_per_launch)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    if (T < 1 || n < T || n % T != 0) return fail(OMT_EINVAL, "need T >= 1 dividing n (T %d, n %lld)", T, (long long)n);
+    if (rows_per_wave < 0) return fail(OMT_EINVAL, "rows_per_wave < 0");
+    const int rows = rows_per_wave > 0 ? rows_per_wave : default_rows(h, T);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, h->stream));
+    omt_status s = OMT_OK;
+    for (int64_t q = 0; q < n / T && s == OMT_OK; ++q) s = step_launch(h, T, rows, T == 1);
+    HIP_TRY(hipEventRecord(e1, h->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != OMT_OK) return s;
+    h->have_last = false;
+    if (us_per_launch) *us_per_launch = 1000.0 * double(ms) / double(n / T);
+    return OMT_OK;
+}
+
+omt_status omt_autotune(omt_handle, int32_t, int32_t *, int32_t *, double *)
+{
+    return fail(OMT_EUNSUPPORTED, "autotune not built yet");
+}
+
+omt_status omt_batch_workspace_bytes(int32_t, const omt_params *, size_t *)
+{
+    return fail(OMT_EUNSUPPORTED, "batched mode not built yet");
+}
+omt_status omt_batch_create(int32_t, const omt_params *, const void *const *, const void *const *, void *, size_t,
+                            void *, omt_batch_handle *)
+{
+    return fail(OMT_EUNSUPPORTED, "batched mode not built yet");
+}
+omt_status omt_batch_solve(omt_batch_handle, int64_t, double, int32_t, omt_info *)
+{
+    return fail(OMT_EUNSUPPORTED, "batched mode not built yet");
+}
+omt_status omt_batch_distance(omt_batch_handle, double *) { return fail(OMT_EUNSUPPORTED, "batched mode not built yet"); }
+omt_status omt_batch_grad(omt_batch_handle, void *const *, void *const *)
+{
+    return fail(OMT_EUNSUPPORTED, "batched mode not built yet");
+}
+omt_status omt_batch_get_state(omt_batch_handle, int32_t, void *, void *, void *)
+{
+    return fail(OMT_EUNSUPPORTED, "batched mode not built yet");
+}
+omt_status omt_batch_destroy(omt_batch_handle) { return OMT_OK; }
+
+const char *omt_strerror(omt_status s)
+{
+    switch (s) {
+        case OMT_OK: return "ok";
+        case OMT_EINVAL: return "invalid argument";
+        case OMT_EGRAPH: return "invalid channel graph";
+        case OMT_EMASS: return "densities carry different mass";
+        case OMT_ESTEP: return "step sizes violate the convergence condition";
+        case OMT_ENOMEM: return "workspace too small";
+        case OMT_EDEVICE: return "HIP error";
+        case OMT_ENOTCONV: return "tolerance not reached";
+        case OMT_EDIVERGED: return "iteration diverged";
+        case OMT_EUNSUPPORTED: return "unsupported by this build";
+        default: return "unknown status";
+    }
+}
+
+const char *omt_last_error(void) { return g_last_error.c_str(); }
+
+int32_t omt_version(void) { return 1; }
+
+}  // extern "C"

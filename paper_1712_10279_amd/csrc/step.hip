@@ -1,0 +1,408 @@
+// Fused PDHG iteration of the vector-OMT method (Sec. 7.2) for gfx950.
+//
+// One wavefront owns a strip of 64 - 2T columns (lanes are columns, so every
+// load and store is a coalesced row segment) and a chunk of rows, and
+// streams down the rows.  Each lane keeps its own column's state in
+// registers; the neighbours a step needs come from the adjacent lane (right
+// potential for grad_y, left flux for div_y) or from the previous row held
+// in registers (flux for div_x).  T iterations are pipelined: stage t works
+// on iteration t+1, one row behind stage t-1, so one pass over HBM advances
+// the strip by T iterations.  The outer T lanes and T rows on each side are a
+// recomputed halo; only the interior is stored.
+//
+// Per pixel and iteration (App. A discretisation, ghosts u_x(m-1,.) = 0 and
+// u_y(., n-1) = 0, Sec. 7.2 updates):
+//   u~  = u + mu grad_x phi                    -> shrink_u(., mu)
+//   w~  = w + nu grad_G phi                    -> shrink_w(., alpha nu)
+//   phi' = phi + tau (div_x(2u'-u) + div_G(2w'-w) + f),   f = rho1 - rho0.
+//
+// Compiled once per channel count (OMT_K) to keep build units small.
+
+#include "omt_kernels.h"
+
+#ifndef OMT_K
+#error "compile with -DOMT_K=<channels>"
+#endif
+
+namespace omt {
+namespace {
+
+// ------------------------------------------------------------ lane moves
+
+__device__ __forceinline__ float lane_next(float v) { return __shfl_down(v, 1u, WAVE); }
+__device__ __forceinline__ float lane_prev(float v) { return __shfl_up(v, 1u, WAVE); }
+__device__ __forceinline__ double lane_next(double v) { return __shfl_down(v, 1u, WAVE); }
+__device__ __forceinline__ double lane_prev(double v) { return __shfl_up(v, 1u, WAVE); }
+
+// ------------------------------------------------------------ shrinks (App. B)
+
+template <typename R>
+__device__ __forceinline__ R shrink_scale(R r, R t)
+{
+    // (1 - t/r) for r >= t, else 0: the factor applied to the block.
+    return (r >= t && r > R(0)) ? R(1) - t / r : R(0);
+}
+
+template <typename R, int K>
+__device__ __forceinline__ void shrink_u(int unorm, R (&bx)[K], R (&by)[K], R t)
+{
+    if (unorm == 0) {  // sum over channels of ||(u_x, u_y)||_2
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const R s = shrink_scale(sqrt(bx[c] * bx[c] + by[c] * by[c]), t);
+            bx[c] = bx[c] * s;
+            by[c] = by[c] * s;
+        }
+    } else if (unorm == 1) {  // element-wise
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            bx[c] = bx[c] * shrink_scale(fabs(bx[c]), t);
+            by[c] = by[c] * shrink_scale(fabs(by[c]), t);
+        }
+    } else {  // one block of all 2k components
+        R r2 = R(0);
+#pragma unroll
+        for (int c = 0; c < K; ++c) r2 = r2 + bx[c] * bx[c];
+#pragma unroll
+        for (int c = 0; c < K; ++c) r2 = r2 + by[c] * by[c];
+        const R s = shrink_scale(sqrt(r2), t);
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            bx[c] = bx[c] * s;
+            by[c] = by[c] * s;
+        }
+    }
+}
+
+template <typename R, int L>
+__device__ __forceinline__ void shrink_w(int wnorm, R (&w)[L], R t)
+{
+    if (wnorm == 0) {
+#pragma unroll
+        for (int e = 0; e < L; ++e) w[e] = w[e] * shrink_scale(fabs(w[e]), t);
+    } else {
+        R r2 = R(0);
+#pragma unroll
+        for (int e = 0; e < L; ++e) r2 = r2 + w[e] * w[e];
+        const R s = shrink_scale(sqrt(r2), t);
+#pragma unroll
+        for (int e = 0; e < L; ++e) w[e] = w[e] * s;
+    }
+}
+
+// ------------------------------------------------------------ one stage
+
+// Iteration of one pixel row r for this lane's column.  pA/pB: potential
+// on rows r and r+1 (hi and, if COMP, lo parts); ux, uy, w: state on row r;
+// carry: 2u'_x - u_x of row r-1 on entry, of row r on exit.
+template <typename R, int K, int L, int LA, bool COMP>
+__device__ __forceinline__ void stage(const StepArgs<R> &a, bool lane_ok, bool last_row, bool last_col,
+                                      const R (&pA)[K], const R (&pAl)[K], const R (&pB)[K], const R (&pBl)[K],
+                                      const R (&ux)[K], const R (&uy)[K], const R (&w)[LA], const R (&f)[K],
+                                      R (&carry)[K], R (&pO)[K], R (&pOl)[K], R (&uxO)[K], R (&uyO)[K],
+                                      R (&wO)[LA])
+{
+    // u-update: shrink_u(u + mu grad_x phi, mu)
+    R bx[K], by[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const R pr = lane_next(pA[c]);
+        R gx = pB[c] - pA[c];
+        R gy = pr - pA[c];
+        if (COMP) {
+            const R prl = lane_next(pAl[c]);
+            gx = gx + (pBl[c] - pAl[c]);
+            gy = gy + (prl - pAl[c]);
+        }
+        bx[c] = last_row ? R(0) : ux[c] + a.mu_h * gx;
+        by[c] = last_col ? R(0) : uy[c] + a.mu_h * gy;
+    }
+    shrink_u<R, K>(a.unorm, bx, by, a.mu);
+
+    // w-update: shrink_w(w + nu grad_G phi, alpha nu), grad_G phi = M^T phi
+    R wt[LA];
+    if (L > 0) {
+#pragma unroll
+        for (int e = 0; e < LA; ++e) {
+            R s = R(0);
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                s = s + a.gm[c * LMAX + e] * pA[c];
+                if (COMP) s = s + a.gm[c * LMAX + e] * pAl[c];
+            }
+            wt[e] = (e < a.l) ? w[e] + a.nu * s : R(0);
+        }
+        shrink_w<R, LA>(a.wnorm, wt, a.anu);
+    }
+
+    if (!lane_ok) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) bx[c] = by[c] = R(0);
+        if (L > 0) {
+#pragma unroll
+            for (int e = 0; e < LA; ++e) wt[e] = R(0);
+        }
+    }
+
+    // phi-update with the extrapolated primal: div_x(2u'-u) + div_G(2w'-w)
+    R wb[LA];
+    if (L > 0) {
+#pragma unroll
+        for (int e = 0; e < LA; ++e) wb[e] = R(2) * wt[e] - w[e];
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const R ubx = R(2) * bx[c] - ux[c];
+        const R uby = R(2) * by[c] - uy[c];
+        const R ubl = lane_prev(uby);
+        const R dx = (((ubx - carry[c]) + uby) - ubl) * a.inv_h;
+        R dg = R(0);
+        if (L > 0) {
+#pragma unroll
+            for (int e = 0; e < LA; ++e) dg = dg + a.gm[c * LMAX + e] * wb[e];
+        }
+        const R inc = a.tau * ((dx - dg) + f[c]);
+        if (COMP) {
+            // error-free sum of (hi, lo) and the increment (TwoSum)
+            const R t = pAl[c] + inc;
+            const R s = pA[c] + t;
+            const R bb = s - pA[c];
+            const R err = (pA[c] - (s - bb)) + (t - bb);
+            pO[c] = lane_ok ? s : R(0);
+            pOl[c] = lane_ok ? err : R(0);
+        } else {
+            pO[c] = lane_ok ? pA[c] + inc : R(0);
+        }
+        carry[c] = ubx;
+        uxO[c] = bx[c];
+        uyO[c] = by[c];
+    }
+    if (L > 0) {
+#pragma unroll
+        for (int e = 0; e < LA; ++e) wO[e] = wt[e];
+    }
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int nwg)
+{
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
+    // contiguous range of tiles (a band of rows) so that halo rows and
+    // columns shared by neighbouring waves hit in that XCD's L2.
+    constexpr int NX = 8;
+    const int x = b % NX, idx = b / NX;
+    const int q = nwg / NX, r = nwg % NX;
+    return (x < r) ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
+}
+
+template <typename R, int K, int L, int T, bool COMP>
+__global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step_kernel(const StepArgs<R> a)
+{
+    constexpr int LA = L > 0 ? L : 1;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int g = xcd_remap(blockIdx.x, a.nwg);
+    const int wc = g % a.ncolw;
+    const int wr = (g / a.ncolw) * STEP_WAVES_PER_WG + (threadIdx.x / WAVE);
+    if (wr >= a.nroww) return;  // whole wave leaves; no barriers follow
+
+    const int j = wc * (WAVE - 2 * T) - T + lane;
+    const bool jin = (j >= 0) && (j < a.n);
+    const bool jout = jin && lane >= T && lane < WAVE - T;
+    const bool last_col = (j == a.n - 1);
+    const int jc = jin ? j : 0;
+    const int i0 = wr * a.rows;
+    const int i1 = min(i0 + a.rows, a.m);
+    const int rs = max(i0 - T, 0);
+    const int re = min(i1 + T - 1, a.m);
+    const int64_t P = a.plane;
+    const int pitch = a.pitch;
+
+    const R *__restrict__ phi = a.phi_in + jc;
+    const float *__restrict__ plo = COMP ? a.plo_in + jc : nullptr;
+    const R *__restrict__ uin = a.u_in + jc;
+    const R *__restrict__ win = a.w_in + jc;
+    const R *__restrict__ fin = a.f + jc;
+
+    // stage-0 inputs of the next row, loaded one step ahead
+    R nA[K], nAl[K], nB[K], nBl[K], nux[K], nuy[K], nw[LA], nf[K];
+    auto load_phi = [&](int r, R (&hi)[K], R (&lo)[K]) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            hi[c] = (jin && r < a.m) ? phi[c * P + (int64_t)r * pitch] : R(0);
+            lo[c] = (COMP && jin && r < a.m) ? R(plo[c * P + (int64_t)r * pitch]) : R(0);
+        }
+    };
+    auto load_rest = [&](int r) {
+        const int64_t o = (int64_t)r * pitch;
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            nux[c] = jin ? uin[c * P + o] : R(0);
+            nuy[c] = jin ? uin[(K + c) * P + o] : R(0);
+            nf[c] = jin ? fin[c * P + o] : R(0);
+        }
+#pragma unroll
+        for (int e = 0; e < LA; ++e) nw[e] = (L > 0 && jin && e < a.l) ? win[e * P + o] : R(0);
+    };
+    load_phi(rs, nA, nAl);
+    load_phi(rs + 1, nB, nBl);
+    load_rest(rs);
+
+    // pipeline registers: outputs of stage t on the previous (P) and the
+    // current (N) step, and each stage's carry and source term
+    R phP[T][K], plP[T][K], phN[T][K], plN[T][K];
+    R uxP[T][K], uyP[T][K], wP[T][LA];
+    R uxN[T][K], uyN[T][K], wN[T][LA];
+    R carry[T][K], fq[T][K];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            phP[t][c] = plP[t][c] = phN[t][c] = plN[t][c] = R(0);
+            uxP[t][c] = uyP[t][c] = uxN[t][c] = uyN[t][c] = R(0);
+            carry[t][c] = fq[t][c] = R(0);
+        }
+#pragma unroll
+        for (int e = 0; e < LA; ++e) wP[t][e] = wN[t][e] = R(0);
+    }
+
+    const int nsteps = (re - rs) + T - 1;
+    for (int s = 0; s < nsteps; ++s) {
+        const int r0 = rs + s;
+        // current stage-0 inputs
+        R cA[K], cAl[K], cB[K], cBl[K], cux[K], cuy[K], cw[LA];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            cA[c] = nA[c];
+            cAl[c] = nAl[c];
+            cB[c] = nB[c];
+            cBl[c] = nBl[c];
+            cux[c] = nux[c];
+            cuy[c] = nuy[c];
+        }
+#pragma unroll
+        for (int e = 0; e < LA; ++e) cw[e] = nw[e];
+#pragma unroll
+        for (int t = T - 1; t > 0; --t) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) fq[t][c] = fq[t - 1][c];
+        }
+#pragma unroll
+        for (int c = 0; c < K; ++c) fq[0][c] = nf[c];
+
+        // prefetch the next row while this one is computed
+        if (r0 + 1 < re) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                nA[c] = cB[c];
+                nAl[c] = cBl[c];
+            }
+            load_phi(r0 + 2, nB, nBl);
+            load_rest(r0 + 1);
+        }
+
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int r = r0 - t;
+            if (r >= rs && r < re) {
+                const bool last_row = (r == a.m - 1);
+                if (t == 0) {
+                    stage<R, K, L, LA, COMP>(a, jin, last_row, last_col, cA, cAl, cB, cBl, cux, cuy, cw, fq[0],
+                                             carry[0], phN[0], plN[0], uxN[0], uyN[0], wN[0]);
+                } else {
+                    stage<R, K, L, LA, COMP>(a, jin, last_row, last_col, phP[t - 1], plP[t - 1], phN[t - 1],
+                                             plN[t - 1], uxP[t - 1], uyP[t - 1], wP[t - 1], fq[t], carry[t],
+                                             phN[t], plN[t], uxN[t], uyN[t], wN[t]);
+                }
+                if (t == T - 1 && jout && r >= i0 && r < i1) {
+                    const int64_t o = (int64_t)r * pitch + j;
+#pragma unroll
+                    for (int c = 0; c < K; ++c) {
+                        a.phi_out[c * P + o] = phN[t][c];
+                        if (COMP) a.plo_out[c * P + o] = float(plN[t][c]);
+                        a.u_out[c * P + o] = uxN[t][c];
+                        a.u_out[(K + c) * P + o] = uyN[t][c];
+                    }
+                    if (L > 0) {
+#pragma unroll
+                        for (int e = 0; e < LA; ++e)
+                            if (e < a.l) a.w_out[e * P + o] = wN[t][e];
+                    }
+                }
+            }
+        }
+        // rotate: this step's outputs become the next step's inputs
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                phP[t][c] = phN[t][c];
+                plP[t][c] = plN[t][c];
+                uxP[t][c] = uxN[t][c];
+                uyP[t][c] = uyN[t][c];
+            }
+#pragma unroll
+            for (int e = 0; e < LA; ++e) wP[t][e] = wN[t][e];
+        }
+    }
+}
+
+template <typename R, int K, int L, int T, bool COMP>
+hipError_t launch_one(const StepLaunch &Lc)
+{
+    const StepArgs<R> &a = *static_cast<const StepArgs<R> *>(Lc.args);
+    hipLaunchKernelGGL((pdhg_step_kernel<R, K, L, T, COMP>), dim3(a.nwg), dim3(WAVE * STEP_WAVES_PER_WG), 0,
+                       Lc.stream, a);
+    return hipGetLastError();
+}
+
+// Blocking depths compiled for this channel count (register budget).
+constexpr bool t_ok(int T) { return T == 1 || T == 2 || (T == 4 && OMT_K <= 5) || (T == 8 && OMT_K <= 3); }
+
+template <int L>
+hipError_t dispatch_T(const StepLaunch &Lc)
+{
+    if (Lc.dtype == 1) {
+        if (Lc.T == 1) return launch_one<double, OMT_K, L, 1, false>(Lc);
+        return hipErrorInvalidValue;
+    }
+    switch (Lc.T) {
+        case 1: return Lc.comp ? launch_one<float, OMT_K, L, 1, true>(Lc) : launch_one<float, OMT_K, L, 1, false>(Lc);
+        case 2: return Lc.comp ? launch_one<float, OMT_K, L, 2, true>(Lc) : launch_one<float, OMT_K, L, 2, false>(Lc);
+#if OMT_K <= 5
+        case 4: return Lc.comp ? launch_one<float, OMT_K, L, 4, true>(Lc) : launch_one<float, OMT_K, L, 4, false>(Lc);
+#endif
+#if OMT_K <= 3
+        case 8: return Lc.comp ? launch_one<float, OMT_K, L, 8, true>(Lc) : launch_one<float, OMT_K, L, 8, false>(Lc);
+#endif
+        default: return hipErrorInvalidValue;
+    }
+}
+
+constexpr int LB_TREE = OMT_K - 1;
+constexpr int LB_FULL = OMT_K * (OMT_K - 1) / 2;
+
+}  // namespace
+
+#define OMT_CAT2(a, b) a##b
+#define OMT_CAT(a, b) OMT_CAT2(a, b)
+
+hipError_t OMT_CAT(launch_step_k, OMT_K)(const StepLaunch &Lc)
+{
+    if (Lc.lb == 0) return dispatch_T<0>(Lc);
+#if OMT_K >= 2
+    if (Lc.lb == LB_TREE) return dispatch_T<LB_TREE>(Lc);
+#endif
+#if OMT_K >= 3
+    if (Lc.lb == LB_FULL) return dispatch_T<LB_FULL>(Lc);
+#endif
+    return hipErrorInvalidValue;
+}
+
+bool OMT_CAT(step_supported_k, OMT_K)(int dtype, int lb, int T, bool comp)
+{
+    const bool lb_ok = lb == 0 || (OMT_K >= 2 && lb == LB_TREE) || (OMT_K >= 3 && lb == LB_FULL);
+    if (!lb_ok) return false;
+    if (dtype == 1) return T == 1 && !comp;
+    return t_ok(T);
+}
+
+}  // namespace omt

@@ -1,0 +1,256 @@
+"""Python binding of ``libomt.so`` (the C ABI of ``include/omt.h``).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  PyTorch provides device memory (the workspace and the caller's
+tensors) and the current stream.  The library is loaded on first use; if it
+is missing the binding raises instead of computing anything elsewhere.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libomt.so")
+
+OK, EINVAL, EGRAPH, EMASS, ESTEP, ENOMEM, EDEVICE, ENOTCONV, EDIVERGED, EUNSUPPORTED = range(10)
+U_L12, U_L1, U_L2 = 0, 1, 2
+W_L1, W_L2 = 0, 1
+F32, F64 = 0, 1
+FLAG_COMPENSATED_PHI = 1
+MAX_CHANNELS = 8
+
+
+class Params(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("k", C.c_int32), ("n_edges", C.c_int32),
+                ("edges", C.POINTER(C.c_int32)), ("edge_cost", C.POINTER(C.c_double)),
+                ("alpha", C.c_double), ("tau", C.c_double), ("mu", C.c_double), ("nu", C.c_double),
+                ("h", C.c_double), ("unorm", C.c_int32), ("wnorm", C.c_int32), ("dtype", C.c_int32),
+                ("flags", C.c_uint32), ("tblock", C.c_int32), ("rows_per_wave", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("residual", C.c_double), ("primal", C.c_double), ("dual", C.c_double),
+                ("rel_gap", C.c_double), ("mass_residual", C.c_double), ("R", C.c_double),
+                ("converged", C.c_int32), ("checks", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class OMTError(RuntimeError):
+    def __init__(self, status, where, detail):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+_lib = None
+
+# every function the header declares, with its argument and result types
+_SIGS = {
+    "omt_params_init": (None, [C.POINTER(Params)]),
+    "omt_resolve_params": (C.c_int, [C.POINTER(Params)] + [C.POINTER(C.c_double)] * 4),
+    "omt_workspace_bytes": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_size_t)]),
+    "omt_create": (C.c_int, [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                             C.POINTER(C.c_void_p)]),
+    "omt_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.POINTER(Info)]),
+    "omt_distance": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(Info)]),
+    "omt_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "omt_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "omt_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "omt_destroy": (C.c_int, [C.c_void_p]),
+    "omt_batch_workspace_bytes": (C.c_int, [C.c_int32, C.POINTER(Params), C.POINTER(C.c_size_t)]),
+    "omt_batch_create": (C.c_int, [C.c_int32, C.POINTER(Params), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                   C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "omt_batch_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.POINTER(Info)]),
+    "omt_batch_distance": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "omt_batch_grad": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    "omt_batch_get_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "omt_batch_destroy": (C.c_int, [C.c_void_p]),
+    "omt_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double)]),
+    "omt_time_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_double)]),
+    "omt_strerror": (C.c_char_p, [C.c_int]),
+    "omt_last_error": (C.c_char_p, []),
+    "omt_version": (C.c_int32, []),
+}
+
+
+def lib():
+    """The loaded ``libomt.so``; raises if the HIP library was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1712_10279_amd/build.py "
+                               "(the solver has no other implementation)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, where, allow=()):
+    if status != OK and status not in allow:
+        detail = lib().omt_last_error().decode()
+        raise OMTError(status, where, detail)
+    return status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+@dataclass
+class Config:
+    alpha: float = 1.0
+    tau: float = 1.0
+    cost: object = None
+    unorm: int = U_L12
+    wnorm: int = W_L1
+    mu: float = 0.0
+    nu: float = 0.0
+    h: float = 0.0
+    compensated: bool = False
+    tblock: int = 0
+    rows_per_wave: int = 0
+
+
+def make_params(m, n, k, edges, cfg: Config, dtype: int):
+    """(Params, keep-alive arrays) for the C ABI."""
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    p = Params()
+    lib().omt_params_init(C.byref(p))
+    p.m, p.n, p.k, p.n_edges = int(m), int(n), int(k), int(e.shape[0])
+    p.edges = e.ctypes.data_as(C.POINTER(C.c_int32)) if e.size else C.POINTER(C.c_int32)()
+    cost = None
+    if cfg.cost is not None:
+        cost = np.ascontiguousarray(np.asarray(cfg.cost, dtype=np.float64).reshape(-1))
+        p.edge_cost = cost.ctypes.data_as(C.POINTER(C.c_double))
+    p.alpha, p.tau, p.mu, p.nu, p.h = float(cfg.alpha), float(cfg.tau), float(cfg.mu), float(cfg.nu), float(cfg.h)
+    p.unorm, p.wnorm, p.dtype = int(cfg.unorm), int(cfg.wnorm), int(dtype)
+    p.flags = FLAG_COMPENSATED_PHI if cfg.compensated else 0
+    p.tblock, p.rows_per_wave = int(cfg.tblock), int(cfg.rows_per_wave)
+    return p, (e, cost)
+
+
+def resolve_params(m, n, k, edges, **kw):
+    """Host-only: validated (h, mu, nu, lambda_max) of a problem (Sec. 7.2)."""
+    dtype = F64 if kw.pop("dtype", "f32") in ("f64", F64) else F32
+    p, keep = make_params(m, n, k, edges, Config(**kw), dtype)
+    out = [C.c_double() for _ in range(4)]
+    _check(lib().omt_resolve_params(C.byref(p), *[C.byref(o) for o in out]), "omt_resolve_params")
+    return tuple(o.value for o in out)
+
+
+def workspace_bytes(m, n, k, edges, dtype="f32", **kw):
+    p, keep = make_params(m, n, k, edges, Config(**kw), F64 if dtype in ("f64", F64) else F32)
+    b = C.c_size_t()
+    _check(lib().omt_workspace_bytes(C.byref(p), C.byref(b)), "omt_workspace_bytes")
+    return b.value
+
+
+class Solver:
+    """One transport problem on the GPU (omt_create ... omt_destroy)."""
+
+    def __init__(self, rho0, rho1, edges=None, **kw):
+        torch = _torch()
+        if rho0.dim() != 3 or rho0.shape != rho1.shape:
+            raise ValueError("rho0 and rho1 must both be (m, n, k)")
+        if not (rho0.is_cuda and rho1.is_cuda):
+            raise ValueError("rho0 and rho1 must be on the GPU")
+        if rho0.dtype not in (torch.float32, torch.float64) or rho1.dtype != rho0.dtype:
+            raise ValueError("rho0 and rho1 must share dtype float32 or float64")
+        self.dtype = rho0.dtype
+        self.m, self.n, self.k = (int(s) for s in rho0.shape)
+        self.edges = np.zeros((0, 2), np.int32) if edges is None else np.asarray(edges, np.int32).reshape(-1, 2)
+        self.l = int(self.edges.shape[0])
+        self.cfg = Config(**kw)
+        dt = F64 if self.dtype == torch.float64 else F32
+        self._p, self._keep = make_params(self.m, self.n, self.k, self.edges, self.cfg, dt)
+        nbytes = C.c_size_t()
+        _check(lib().omt_workspace_bytes(C.byref(self._p), C.byref(nbytes)), "omt_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=rho0.device)
+        self.device = rho0.device
+        r0 = rho0.contiguous()
+        r1 = rho1.contiguous()
+        h = C.c_void_p()
+        _check(lib().omt_create(C.byref(self._p), _ptr(r0), _ptr(r1), _ptr(self.workspace), nbytes.value,
+                                _stream_ptr(), C.byref(h)), "omt_create")
+        self._h = h
+        self.info = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.omt_destroy(h)
+            self._h = None
+
+    def solve(self, max_iters, tol=0.0, check_every=64, allow_notconv=True):
+        info = Info()
+        allow = (ENOTCONV,) if allow_notconv else ()
+        _check(lib().omt_solve(self._h, int(max_iters), float(tol), int(check_every), C.byref(info)),
+               "omt_solve", allow)
+        self.info = info.as_dict()
+        return self.info
+
+    def distance(self):
+        v = C.c_double()
+        info = Info()
+        _check(lib().omt_distance(self._h, C.byref(v), C.byref(info)), "omt_distance")
+        return v.value, info.as_dict()
+
+    def grad(self):
+        torch = _torch()
+        d0 = torch.empty((self.m, self.n, self.k), dtype=self.dtype, device=self.device)
+        d1 = torch.empty_like(d0)
+        _check(lib().omt_grad(self._h, _ptr(d0), _ptr(d1)), "omt_grad")
+        return d0, d1
+
+    def get_state(self):
+        torch = _torch()
+        phi = torch.empty((self.m, self.n, self.k), dtype=self.dtype, device=self.device)
+        u = torch.empty((self.m, self.n, self.k, 2), dtype=self.dtype, device=self.device)
+        w = torch.zeros((self.m, self.n, max(self.l, 1)), dtype=self.dtype, device=self.device)
+        _check(lib().omt_get_state(self._h, _ptr(phi), _ptr(u), _ptr(w) if self.l else C.c_void_p(0)),
+               "omt_get_state")
+        return {"phi": phi, "u": u, "w": w[:, :, : self.l]}
+
+    def set_state(self, phi=None, u=None, w=None):
+        args = [_ptr(None if t is None else t.contiguous()) for t in (phi, u, w)]
+        keep = [t.contiguous() if t is not None else None for t in (phi, u, w)]
+        args = [_ptr(t) for t in keep]
+        _check(lib().omt_set_state(self._h, *args), "omt_set_state")
+
+    def time_steps(self, T, rows_per_wave, n):
+        us = C.c_double()
+        _check(lib().omt_time_steps(self._h, int(T), int(rows_per_wave), int(n), C.byref(us)), "omt_time_steps")
+        return us.value
+
+    def autotune(self, iters_per_trial=64):
+        t, r, us = C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().omt_autotune(self._h, int(iters_per_trial), C.byref(t), C.byref(r), C.byref(us)),
+               "omt_autotune")
+        return t.value, r.value, us.value
+
+
+def distance(rho0, rho1, edges=None, max_iters=10000, tol=0.0, check_every=64, **kw):
+    """V(rho0, rho1) of the discrete problem (App. A) after the solve."""
+    s = Solver(rho0, rho1, edges, **kw)
+    s.solve(max_iters, tol, check_every)
+    return s.distance()[0]

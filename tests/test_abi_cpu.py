@@ -1,0 +1,87 @@
+"""CPU checks of the C ABI library: it loads, exports every symbol
+include/omt.h declares, and its host-only calls validate parameters and
+compute the step sizes of Sec. 7.2 (no device work is done here)."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1712_10279_amd import omt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "omt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(omt_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 20
+    L = omt.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(omt._SIGS), set(names) ^ set(omt._SIGS)
+    assert omt.lib().omt_version() >= 1
+
+
+def test_step_sizes_follow_the_rule():
+    h, mu, nu, lm = omt.resolve_params(33, 33, 3, [(0, 1), (0, 2), (1, 2)], tau=3.0)
+    assert h == pytest.approx(1 / 32)
+    assert mu == pytest.approx(1 / (32 * 3 * 32 ** 2))
+    assert lm == pytest.approx(3.0, abs=1e-12)
+    assert nu == pytest.approx(1 / (4 * 3 * 3.0))
+    h, mu, nu, lm = omt.resolve_params(17, 9, 1, np.zeros((0, 2)), tau=1.0)
+    assert mu == pytest.approx(1 / (16 * 16 ** 2)) and nu == 0.0 and lm == 0.0
+    _, _, _, lm = omt.resolve_params(8, 8, 8, [(c, c + 1) for c in range(7)])
+    assert lm == pytest.approx(2 + 2 * math.cos(math.pi / 8), abs=1e-12)
+
+
+@pytest.mark.parametrize("edges,kw,status", [
+    ([(1, 0)], {}, omt.EGRAPH),                  # a >= b
+    ([(0, 3)], {}, omt.EGRAPH),                  # node out of range
+    ([(0, 1), (0, 1)], {}, omt.EGRAPH),          # duplicate
+    ([(0, 1)], {"cost": [0.0]}, omt.EGRAPH),     # c <= 0
+    ([(0, 1)], {"alpha": 0.0}, omt.EINVAL),
+    ([(0, 1)], {"tau": -1.0}, omt.EINVAL),
+    ([(0, 1)], {"unorm": 7}, omt.EINVAL),
+    ([(0, 1)], {"mu": 1.0}, omt.ESTEP),          # violates tau mu 8/h^2 + tau nu lmax < 1
+    ([(0, 1)], {"nu": 10.0}, omt.ESTEP),
+])
+def test_invalid_parameters(edges, kw, status):
+    with pytest.raises(omt.OMTError) as e:
+        omt.resolve_params(10, 12, 3, edges, **kw)
+    assert e.value.status == status
+
+
+def test_size_limits():
+    with pytest.raises(omt.OMTError) as e:
+        omt.resolve_params(1, 10, 3, [])
+    assert e.value.status == omt.EINVAL
+    with pytest.raises(omt.OMTError) as e:
+        omt.resolve_params(10, 10, 9, [])
+    assert e.value.status == omt.EUNSUPPORTED
+    with pytest.raises(omt.OMTError) as e:
+        omt.resolve_params(10, 10, 0, [])
+    assert e.value.status == omt.EINVAL
+
+
+def test_workspace_size_grows_with_problem():
+    a = omt.workspace_bytes(256, 256, 3, [(0, 1), (0, 2), (1, 2)])
+    b = omt.workspace_bytes(1024, 1024, 8, [(c, c + 1) for c in range(7)])
+    c = omt.workspace_bytes(1024, 1024, 8, [(c, c + 1) for c in range(7)], compensated=True)
+    d = omt.workspace_bytes(1024, 1024, 8, [(c, c + 1) for c in range(7)], dtype="f64")
+    # f, 2 x phi, 2 x u (2k planes), 2 x w: (7k + 2l) planes
+    assert b >= (7 * 8 + 2 * 7) * 1024 * 1024 * 4
+    assert a < b < c and d >= 2 * (7 * 8 + 2 * 7) * 1024 * 1024 * 4
+    assert omt.workspace_bytes(33, 70, 3, []) % 256 == 0
+
+
+def test_status_strings():
+    L = omt.lib()
+    for s in range(10):
+        assert L.omt_strerror(s)

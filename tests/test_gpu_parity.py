@@ -1,0 +1,246 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 runs must match the oracle element by element to 1e-9 (relative to the
+largest entry), which catches any indexing or ordering mistake; FP32 runs
+must match V to 1e-4 relative and the exported potential Phi (mean removed
+per mass class) to 1e-3 max-abs at equal iteration counts and equal tau.
+Sizes span several wavefront strips (62 columns each at T = 1) and chunks
+of rows with ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import cast_inputs, cuda, gpu_state_np, note, oracle_run, to_dev
+from paper_1712_10279_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(torch, rho0, rho1, edges, dtype, **kw):
+    from paper_1712_10279_amd import omt
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    return omt.Solver(to_dev(torch, rho0, tdt), to_dev(torch, rho1, tdt), edges, **kw)
+
+
+def _cmp_state(g, r, tol, what=""):
+    st = r["state"]
+    scale = max(np.abs(st["phi"]).max(), 1e-30)
+    uscale = max(np.abs(st["ux"]).max(), np.abs(st["uy"]).max(), 1e-30)
+    e_phi = np.abs(g["phi"] - st["phi"]).max() / scale
+    e_ux = np.abs(g["u"][..., 0] - st["ux"]).max() / uscale
+    e_uy = np.abs(g["u"][..., 1] - st["uy"]).max() / uscale
+    e_w = 0.0
+    if st["w"].size:
+        wscale = max(np.abs(st["w"]).max(), 1e-30)
+        e_w = np.abs(g["w"] - st["w"]).max() / wscale
+    note(f"{what} rel err phi {e_phi:.2e} ux {e_ux:.2e} uy {e_uy:.2e} w {e_w:.2e}")
+    assert e_phi <= tol and e_ux <= tol and e_uy <= tol and e_w <= tol
+
+
+def test_small_fp64_matches_oracle_elementwise():
+    """32x32, k=3 triangle, alpha 1, FP64, 10,000 iterations."""
+    torch = cuda()
+    d = I.small_fp64()
+    note("case: 32x32 k3 triangle fp64 10000 iterations")
+    r = oracle_run(d["rho0"], d["rho1"], d["edges"], d["iters"], alpha=d["alpha"], tau=d["tau"])
+    s = _solver(torch, d["rho0"], d["rho1"], d["edges"], "f64", alpha=d["alpha"], tau=d["tau"])
+    info = s.solve(d["iters"], 0.0, 64)
+    assert info["iters"] == d["iters"]
+    V, _ = s.distance()
+    assert abs(V - r["primal"]) <= 1e-9 * r["primal"]
+    assert abs(info["dual"] - r["dual"]) <= 1e-9 * abs(r["primal"])
+    assert abs(info["residual"] - r["residual"]) <= 1e-6 * r["residual"]
+    _cmp_state(gpu_state_np(s), r, 1e-9, "32x32 fp64")
+    d0, d1 = s.grad()
+    Phi = d0.cpu().numpy()
+    assert np.abs(Phi - r["Phi"]).max() <= 1e-9 * np.abs(r["Phi"]).max()
+    assert np.array_equal(d1.cpu().numpy(), -Phi)
+
+
+@pytest.mark.parametrize("m,n,k,edges,iters", [
+    (70, 150, 3, I.TRIANGLE, 300),        # 3 strips, ragged rows and columns
+    (129, 64, 1, np.zeros((0, 2)), 300),  # scalar OMT (l = 0)
+    (64, 80, 8, I.path_edges(8), 200),    # the 8-channel path of the large workload
+    (33, 191, 2, [(0, 1)], 250),
+    (40, 70, 5, I.complete_edges(5), 150),
+    (2, 2, 3, I.TRIANGLE, 50),            # smallest grid
+    (3, 130, 4, I.path_edges(4), 120),
+    (130, 3, 3, I.TRIANGLE, 120),
+])
+def test_fp64_shapes_and_graphs(m, n, k, edges, iters):
+    torch = cuda()
+    r0, r1 = I.random_pair(21, m, n, k)
+    note(f"case: fp64 {m}x{n} k{k} l{len(edges)} {iters} it")
+    r = oracle_run(r0, r1, edges, iters, alpha=0.7, tau=I.default_tau(m, n))
+    s = _solver(torch, r0, r1, edges, "f64", alpha=0.7, tau=I.default_tau(m, n))
+    s.solve(iters, 0.0, 50)
+    _cmp_state(gpu_state_np(s), r, 1e-10, f"{m}x{n}k{k}")
+    assert abs(s.distance()[0] - r["primal"]) <= 1e-10 * r["primal"]
+
+
+@pytest.mark.parametrize("unorm", [0, 1, 2])
+@pytest.mark.parametrize("wnorm", [0, 1])
+def test_fp64_all_norms(unorm, wnorm):
+    torch = cuda()
+    r0, r1 = I.random_pair(22, 48, 90, 3)
+    note(f"case: fp64 norms u{unorm} w{wnorm}")
+    r = oracle_run(r0, r1, I.TRIANGLE, 400, alpha=0.5, unorm=unorm, wnorm=wnorm)
+    s = _solver(torch, r0, r1, I.TRIANGLE, "f64", alpha=0.5, unorm=unorm, wnorm=wnorm)
+    info = s.solve(400, 0.0, 64)
+    _cmp_state(gpu_state_np(s), r, 1e-10, f"norms {unorm}{wnorm}")
+    assert abs(info["primal"] - r["primal"]) <= 1e-10 * r["primal"]
+
+
+def test_fp64_weighted_edges_and_given_steps():
+    torch = cuda()
+    r0, r1 = I.random_pair(23, 40, 66, 3)
+    cost = [0.5, 2.0, 1.3]
+    h = 1 / 65
+    kw = dict(alpha=1.2, tau=2.0, cost=cost, mu=h * h / 80, nu=0.02)
+    note("case: fp64 weighted edges, given steps")
+    r = oracle_run(r0, r1, I.TRIANGLE, 300, **kw)
+    s = _solver(torch, r0, r1, I.TRIANGLE, "f64", **kw)
+    s.solve(300, 0.0, 64)
+    _cmp_state(gpu_state_np(s), r, 1e-10, "weighted")
+
+
+def test_fp64_convergence_check_cadence():
+    """Stops at the same check as the oracle and reports the same residual."""
+    torch = cuda()
+    r0, r1 = I.random_pair(24, 24, 24, 3)
+    note("case: fp64 24x24 to tol 1e-6")
+    r = oracle_run(r0, r1, I.TRIANGLE, 200000, tol=1e-6, check_every=64)
+    s = _solver(torch, r0, r1, I.TRIANGLE, "f64")
+    info = s.solve(200000, 1e-6, 64)
+    assert r["converged"] and info["converged"]
+    assert info["iters"] == r["iters"]
+    assert abs(info["residual"] - r["residual"]) <= 1e-6 * r["residual"]
+    assert abs(info["primal"] - r["primal"]) <= 1e-9 * r["primal"]
+
+
+def test_fp32_matches_oracle_within_tolerance():
+    """FP32 iterates, FP64 reductions: V to 1e-4, Phi to 1e-3 max-abs."""
+    torch = cuda()
+    r0, r1 = I.random_pair(25, 96, 130, 3, bumps=4)
+    r0c, r1c = cast_inputs(r0, r1, "f32")
+    note("case: fp32 96x130 k3 3000 it")
+    r = oracle_run(r0c, r1c, I.TRIANGLE, 3000, tau=3.0)
+    s = _solver(torch, r0, r1, I.TRIANGLE, "f32", tau=3.0)
+    s.solve(3000, 0.0, 64)
+    V, _ = s.distance()
+    relV = abs(V - r["primal"]) / r["primal"]
+    Phi = s.grad()[0].double().cpu().numpy()
+    ePhi = np.abs(Phi - r["Phi"]).max()
+    note(f"fp32: rel V {relV:.2e}, max |dPhi| {ePhi:.2e}")
+    assert relV <= 1e-4
+    assert ePhi <= 1e-3
+
+
+def test_fp32_compensated_potential_matches_oracle():
+    torch = cuda()
+    r0, r1 = I.random_pair(26, 96, 130, 3, bumps=4)
+    r0c, r1c = cast_inputs(r0, r1, "f32")
+    note("case: fp32 compensated 96x130 k3 3000 it")
+    r = oracle_run(r0c, r1c, I.TRIANGLE, 3000, tau=3.0)
+    s = _solver(torch, r0, r1, I.TRIANGLE, "f32", tau=3.0, compensated=True)
+    s.solve(3000, 0.0, 64)
+    V, _ = s.distance()
+    Phi = s.grad()[0].double().cpu().numpy()
+    relV = abs(V - r["primal"]) / r["primal"]
+    ePhi = np.abs(Phi - r["Phi"]).max()
+    note(f"fp32 comp: rel V {relV:.2e}, max |dPhi| {ePhi:.2e}")
+    assert relV <= 1e-4 and ePhi <= 1e-3
+
+
+@pytest.mark.parametrize("k,edges", [(1, np.zeros((0, 2))), (3, I.TRIANGLE), (3, [(0, 1), (1, 2)]),
+                                     (5, I.path_edges(5)), (8, I.path_edges(8)), (2, [(0, 1)])])
+@pytest.mark.parametrize("comp", [False, True])
+def test_temporal_blocking_is_bit_identical(k, edges, comp):
+    """T iterations per pass give the same bits as T single iterations."""
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    m, n = 77, 200
+    r0, r1 = I.random_pair(27, m, n, k)
+    ref = _solver(torch, r0, r1, edges, "f32", compensated=comp, tau=3.0)
+    ref.time_steps(1, 0, 48)
+    a = ref.get_state()
+    for T in (2, 4, 8):
+        for rows in (0, 5, 16):
+            s = _solver(torch, r0, r1, edges, "f32", compensated=comp, tau=3.0)
+            try:
+                s.time_steps(T, rows, 48)
+            except omt.OMTError as e:
+                assert e.status == omt.EUNSUPPORTED
+                continue
+            b = s.get_state()
+            note(f"case: k{k} T{T} rows{rows} comp{comp}")
+            for key in ("phi", "u", "w"):
+                assert torch.equal(a[key], b[key]), (k, T, rows, key)
+
+
+def test_rows_per_wave_does_not_change_bits():
+    torch = cuda()
+    r0, r1 = I.random_pair(28, 100, 140, 3)
+    out = []
+    for rows in (1, 3, 7, 32, 100):
+        s = _solver(torch, r0, r1, I.TRIANGLE, "f32", rows_per_wave=rows)
+        s.solve(130, 0.0, 64)
+        out.append(s.get_state())
+    for o in out[1:]:
+        for key in ("phi", "u", "w"):
+            assert torch.equal(out[0][key], o[key])
+
+
+def test_state_roundtrip_and_warm_start():
+    torch = cuda()
+    r0, r1 = I.random_pair(29, 40, 70, 3)
+    a = _solver(torch, r0, r1, I.TRIANGLE, "f64")
+    a.solve(200, 0.0, 64)
+    st = a.get_state()
+    b = _solver(torch, r0, r1, I.TRIANGLE, "f64")
+    b.set_state(st["phi"], st["u"], st["w"])
+    st2 = b.get_state()
+    for key in ("phi", "u", "w"):
+        assert torch.equal(st[key], st2[key])
+    a.solve(100, 0.0, 64)
+    b.solve(100, 0.0, 64)
+    s1, s2 = a.get_state(), b.get_state()
+    for key in ("phi", "u", "w"):
+        assert torch.equal(s1[key], s2[key])
+    # ghost components are zeroed on set
+    u = torch.ones_like(st["u"])
+    b.set_state(st["phi"], u, st["w"])
+    ub = b.get_state()["u"]
+    assert torch.all(ub[-1, :, :, 0] == 0) and torch.all(ub[:, -1, :, 1] == 0)
+    assert torch.all(ub[:-1, :, :, 0] == 1) and torch.all(ub[:, :-1, :, 1] == 1)
+
+
+def test_mass_and_nan_errors_on_device():
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    r0, r1 = I.random_pair(30, 16, 16, 3)
+    with pytest.raises(omt.OMTError) as e:
+        _solver(torch, r0, r1 * 1.01, I.TRIANGLE, "f64")
+    assert e.value.status == omt.EMASS
+    bad = r0.copy()
+    bad[3, 4, 1] = np.nan
+    with pytest.raises(omt.OMTError) as e:
+        _solver(torch, bad, r1, I.TRIANGLE, "f32")
+    assert e.value.status == omt.EINVAL
+    # disconnected graph: each class must balance on its own
+    r1b = r1.copy()
+    r1b[:, :, 2] *= 1.5
+    r1b[:, :, :2] *= (r1.sum() - r1b[:, :, 2].sum()) / r1[:, :, :2].sum()
+    with pytest.raises(omt.OMTError) as e:
+        _solver(torch, r0, r1b, [(0, 1)], "f64")
+    assert e.value.status == omt.EMASS
+
+
+def test_distance_of_equal_densities_is_zero():
+    torch = cuda()
+    r0, _ = I.random_pair(31, 50, 61, 3)
+    s = _solver(torch, r0, r0, I.TRIANGLE, "f32")
+    info = s.solve(500, 0.0, 64)
+    assert s.distance()[0] == 0.0
+    assert info["residual"] == 0.0
