@@ -38,7 +38,22 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations for the CPU baseline (0: auto)")
     ap.add_argument("--timing-launches", type=int, default=200)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run plain device-to-device copies of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """Plain copies of a known size: the reference for scaling the HBM byte
+    counters (FETCH_SIZE, WRITE_SIZE) of the profiler."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 5}), flush=True)
 
 
 def _kernel_hash():
@@ -80,6 +95,9 @@ def cpu_baseline(d, iters):
 
 def main():
     a = _parse()
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {a.gpus})",
               file=sys.stderr)

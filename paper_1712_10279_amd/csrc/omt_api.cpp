@@ -28,14 +28,14 @@ hipError_t launch_step_k5(const StepLaunch &);
 hipError_t launch_step_k6(const StepLaunch &);
 hipError_t launch_step_k7(const StepLaunch &);
 hipError_t launch_step_k8(const StepLaunch &);
-bool step_supported_k1(int, int, int, bool);
-bool step_supported_k2(int, int, int, bool);
-bool step_supported_k3(int, int, int, bool);
-bool step_supported_k4(int, int, int, bool);
-bool step_supported_k5(int, int, int, bool);
-bool step_supported_k6(int, int, int, bool);
-bool step_supported_k7(int, int, int, bool);
-bool step_supported_k8(int, int, int, bool);
+bool step_supported_k1(int, int, int, int, bool);
+bool step_supported_k2(int, int, int, int, bool);
+bool step_supported_k3(int, int, int, int, bool);
+bool step_supported_k4(int, int, int, int, bool);
+bool step_supported_k5(int, int, int, int, bool);
+bool step_supported_k6(int, int, int, int, bool);
+bool step_supported_k7(int, int, int, int, bool);
+bool step_supported_k8(int, int, int, int, bool);
 
 hipError_t launch_step(const StepLaunch &L)
 {
@@ -52,17 +52,17 @@ hipError_t launch_step(const StepLaunch &L)
     }
 }
 
-bool step_supported(int dtype, int k, int lb, int T, bool comp)
+bool step_supported(int dtype, int k, int gk, int lb, int T, bool comp)
 {
     switch (k) {
-        case 1: return step_supported_k1(dtype, lb, T, comp);
-        case 2: return step_supported_k2(dtype, lb, T, comp);
-        case 3: return step_supported_k3(dtype, lb, T, comp);
-        case 4: return step_supported_k4(dtype, lb, T, comp);
-        case 5: return step_supported_k5(dtype, lb, T, comp);
-        case 6: return step_supported_k6(dtype, lb, T, comp);
-        case 7: return step_supported_k7(dtype, lb, T, comp);
-        case 8: return step_supported_k8(dtype, lb, T, comp);
+        case 1: return step_supported_k1(dtype, gk, lb, T, comp);
+        case 2: return step_supported_k2(dtype, gk, lb, T, comp);
+        case 3: return step_supported_k3(dtype, gk, lb, T, comp);
+        case 4: return step_supported_k4(dtype, gk, lb, T, comp);
+        case 5: return step_supported_k5(dtype, gk, lb, T, comp);
+        case 6: return step_supported_k6(dtype, gk, lb, T, comp);
+        case 7: return step_supported_k7(dtype, gk, lb, T, comp);
+        case 8: return step_supported_k8(dtype, gk, lb, T, comp);
         default: return false;
     }
 }
@@ -132,7 +132,7 @@ double jacobi_lambda_max(std::vector<double> A, int k)
 }
 
 struct Resolved {
-    int m, n, k, l, lb;
+    int m, n, k, l, gk, lb;
     std::vector<int32_t> edges;
     std::vector<double> cost;
     double alpha, tau, mu, nu, h, lmax;
@@ -180,7 +180,28 @@ omt_status resolve(const omt_params *p, Resolved &r)
             if (r.edges[2 * f] == a && r.edges[2 * f + 1] == b) return fail(OMT_EGRAPH, "duplicate edge (%d, %d)", a, b);
     }
     if (r.l > LMAX) return fail(OMT_EUNSUPPORTED, "%d edges exceed %d", r.l, LMAX);
-    r.lb = edge_bucket(r.k, r.l);
+    // graph kind: compiled incidence for the path and the complete graph in
+    // canonical edge order, the dense matrix otherwise
+    {
+        bool path = r.l == r.k - 1, full = r.l == r.k * (r.k - 1) / 2;
+        for (int e = 0; e < r.l && path; ++e) path = r.edges[2 * e] == e && r.edges[2 * e + 1] == e + 1;
+        int e = 0;
+        for (int a = 0; a < r.k && full; ++a)
+            for (int b = a + 1; b < r.k && full; ++b, ++e) full = r.edges[2 * e] == a && r.edges[2 * e + 1] == b;
+        if (r.l == 0) {
+            r.gk = G_NONE;
+            r.lb = 0;
+        } else if (path) {
+            r.gk = G_PATH;
+            r.lb = r.l;
+        } else if (full) {
+            r.gk = G_COMPLETE;
+            r.lb = r.l;
+        } else {
+            r.gk = G_DENSE;
+            r.lb = dense_bucket(r.k, r.l);
+        }
+    }
     r.alpha = p->alpha;
     r.tau = p->tau;
     r.unorm = p->unorm;
@@ -345,7 +366,9 @@ void fill_step_args(StepArgs<R> &a, const omt_ctx *h, int T, int rows, bool w_in
     a.tau = R(r.tau);
     a.inv_h = R(1.0 / r.h);
     for (int q = 0; q < KMAX * LMAX; ++q) a.gm[q] = R(0);
+    for (int q = 0; q < LMAX; ++q) a.ic[q] = R(0);
     for (int e = 0; e < r.l; ++e) {
+        a.ic[e] = R(1.0 / r.cost[e]);
         a.gm[r.edges[2 * e] * LMAX + e] = R(1.0 / r.cost[e]);
         a.gm[r.edges[2 * e + 1] * LMAX + e] = R(-1.0 / r.cost[e]);
     }
@@ -367,8 +390,9 @@ int default_rows(const omt_ctx *h, int T)
 omt_status step_launch(omt_ctx *h, int T, int rows, bool w_inplace)
 {
     const Resolved &r = h->r;
-    if (!step_supported(r.dtype, r.k, r.lb, T, r.comp))
-        return fail(OMT_EUNSUPPORTED, "no step kernel for dtype %d, k %d, edge bucket %d, T %d", r.dtype, r.k, r.lb, T);
+    if (!step_supported(r.dtype, r.k, r.gk, r.lb, T, r.comp))
+        return fail(OMT_EUNSUPPORTED, "no step kernel for dtype %d, k %d, graph kind %d (%d edges), T %d%s", r.dtype,
+                    r.k, r.gk, r.lb, T, r.comp ? ", compensated" : "");
     if (T > 1) w_inplace = false;  // halo lanes of a pipelined step must see the old w
     const int ncolw = (r.n + (WAVE - 2 * T) - 1) / (WAVE - 2 * T);
     const int nroww = (r.m + rows - 1) / rows;
@@ -376,6 +400,7 @@ omt_status step_launch(omt_ctx *h, int T, int rows, bool w_inplace)
     StepLaunch Lc;
     Lc.dtype = r.dtype;
     Lc.k = r.k;
+    Lc.gk = r.gk;
     Lc.lb = r.lb;
     Lc.T = T;
     Lc.comp = r.comp;

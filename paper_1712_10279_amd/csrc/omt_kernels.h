@@ -13,14 +13,17 @@ constexpr int LMAX = 28;   // edges (complete graph on 8 nodes)
 constexpr int WAVE = 64;
 constexpr int STEP_WAVES_PER_WG = 4;
 
-// Capacity buckets for the edge count: the kernels are compiled for a few
-// capacities per channel count and the unused edges carry zero weight.
-inline int edge_bucket(int k, int l)
+// Channel graphs the step kernel is compiled for.  The path (edges (c, c+1))
+// and the complete graph (all a < b in lexicographic order) get their
+// incidence structure at compile time; any other graph uses the dense
+// matrix M = D diag(1/c) with the edge count rounded up to a bucket (the
+// unused edges carry zero weight).
+enum GraphKind { G_NONE = 0, G_PATH = 1, G_COMPLETE = 2, G_DENSE = 3 };
+
+inline int dense_bucket(int k, int l)
 {
-    if (l == 0) return 0;
-    if (k == 2) return 1;
-    if (l <= k - 1) return k - 1;          // trees (paths, stars)
-    return k * (k - 1) / 2;                // anything else: room for K_k
+    if (l <= k - 1) return k - 1;  // trees
+    return k * (k - 1) / 2;        // room for K_k
 }
 
 // Arguments of one fused PDHG launch (T iterations).  Arrays are SoA planes
@@ -46,12 +49,14 @@ struct StepArgs {
     R mu, mu_h;            // mu, mu / h
     R nu, anu;             // nu, alpha nu
     R tau, inv_h;          // tau, 1 / h
-    R gm[KMAX * LMAX];     // M = D diag(1/c), row c, column e at gm[c * LMAX + e]
+    R ic[LMAX];            // 1 / c_e
+    R gm[KMAX * LMAX];     // dense graphs: M = D diag(1/c), row c, column e at gm[c * LMAX + e]
 };
 
 struct StepLaunch {
     int dtype;   // 0 f32, 1 f64
-    int k, lb;   // channels, edge bucket
+    int k, gk;   // channels, GraphKind
+    int lb;      // edges compiled for
     int T;       // iterations per launch
     bool comp;   // compensated potential
     const void *args;
@@ -60,7 +65,7 @@ struct StepLaunch {
 
 // Defined once per channel count in step_k<K>.hip.
 hipError_t launch_step(const StepLaunch &L);
-bool step_supported(int dtype, int k, int lb, int T, bool comp);
+bool step_supported(int dtype, int k, int gk, int lb, int T, bool comp);
 
 // ---------------------------------------------------------------- auxiliary
 

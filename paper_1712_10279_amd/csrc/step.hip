@@ -90,12 +90,32 @@ __device__ __forceinline__ void shrink_w(int wnorm, R (&w)[L], R t)
     }
 }
 
+// ------------------------------------------------------------ channel graph
+
+// Endpoints (a_e, b_e), a_e < b_e, of edge e of the compiled graph kinds.
+constexpr int complete_row_start(int K, int a) { return a * (K - 1) - a * (a - 1) / 2; }
+template <int GK, int K>
+constexpr int edge_a(int e)
+{
+    if (GK == G_PATH) return e;
+    int a = 0;
+    while (a + 1 < K && complete_row_start(K, a + 1) <= e) ++a;
+    return a;
+}
+template <int GK, int K>
+constexpr int edge_b(int e)
+{
+    if (GK == G_PATH) return e + 1;
+    const int a = edge_a<GK, K>(e);
+    return a + 1 + (e - complete_row_start(K, a));
+}
+
 // ------------------------------------------------------------ one stage
 
 // Iteration of one pixel row r for this lane's column.  pA/pB: potential
 // on rows r and r+1 (hi and, if COMP, lo parts); ux, uy, w: state on row r;
 // carry: 2u'_x - u_x of row r-1 on entry, of row r on exit.
-template <typename R, int K, int L, int LA, bool COMP>
+template <typename R, int K, int GK, int L, int LA, bool COMP>
 __device__ __forceinline__ void stage(const StepArgs<R> &a, bool lane_ok, bool last_row, bool last_col,
                                       const R (&pA)[K], const R (&pAl)[K], const R (&pB)[K], const R (&pBl)[K],
                                       const R (&ux)[K], const R (&uy)[K], const R (&w)[LA], const R (&f)[K],
@@ -119,18 +139,26 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, bool lane_ok, bool l
     }
     shrink_u<R, K>(a.unorm, bx, by, a.mu);
 
-    // w-update: shrink_w(w + nu grad_G phi, alpha nu), grad_G phi = M^T phi
+    // w-update: shrink_w(w + nu grad_G phi, alpha nu); (grad_G phi)_e =
+    // (phi_a - phi_b) / c_e (Sec. 3.1), or M^T phi for a dense graph
     R wt[LA];
-    if (L > 0) {
+    if constexpr (L > 0) {
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
             R s = R(0);
+            if constexpr (GK == G_DENSE) {
 #pragma unroll
-            for (int c = 0; c < K; ++c) {
-                s = s + a.gm[c * LMAX + e] * pA[c];
-                if (COMP) s = s + a.gm[c * LMAX + e] * pAl[c];
+                for (int c = 0; c < K; ++c) {
+                    s = s + a.gm[c * LMAX + e] * pA[c];
+                    if (COMP) s = s + a.gm[c * LMAX + e] * pAl[c];
+                }
+                wt[e] = (e < a.l) ? w[e] + a.nu * s : R(0);
+            } else {
+                const int ea = edge_a<GK, K>(e), eb = edge_b<GK, K>(e);
+                s = pA[ea] - pA[eb];
+                if (COMP) s = s + (pAl[ea] - pAl[eb]);
+                wt[e] = w[e] + a.nu * (s * a.ic[e]);
             }
-            wt[e] = (e < a.l) ? w[e] + a.nu * s : R(0);
         }
         shrink_w<R, LA>(a.wnorm, wt, a.anu);
     }
@@ -146,7 +174,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, bool lane_ok, bool l
 
     // phi-update with the extrapolated primal: div_x(2u'-u) + div_G(2w'-w)
     R wb[LA];
-    if (L > 0) {
+    if constexpr (L > 0) {
 #pragma unroll
         for (int e = 0; e < LA; ++e) wb[e] = R(2) * wt[e] - w[e];
     }
@@ -156,10 +184,18 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, bool lane_ok, bool l
         const R uby = R(2) * by[c] - uy[c];
         const R ubl = lane_prev(uby);
         const R dx = (((ubx - carry[c]) + uby) - ubl) * a.inv_h;
+        // div_G(w) = -D diag(1/c) w: dg is D diag(1/c) w, accumulated in edge order
         R dg = R(0);
-        if (L > 0) {
+        if constexpr (L > 0) {
 #pragma unroll
-            for (int e = 0; e < LA; ++e) dg = dg + a.gm[c * LMAX + e] * wb[e];
+            for (int e = 0; e < LA; ++e) {
+                if constexpr (GK == G_DENSE) {
+                    dg = dg + a.gm[c * LMAX + e] * wb[e];
+                } else {
+                    if (edge_a<GK, K>(e) == c) dg = dg + a.ic[e] * wb[e];
+                    if (edge_b<GK, K>(e) == c) dg = dg - a.ic[e] * wb[e];
+                }
+            }
         }
         const R inc = a.tau * ((dx - dg) + f[c]);
         if (COMP) {
@@ -194,7 +230,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nwg)
     return (x < r) ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
 }
 
-template <typename R, int K, int L, int T, bool COMP>
+template <typename R, int K, int GK, int L, int T, bool COMP>
 __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step_kernel(const StepArgs<R> a)
 {
     constexpr int LA = L > 0 ? L : 1;
@@ -305,10 +341,10 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step_kernel(cons
             if (r >= rs && r < re) {
                 const bool last_row = (r == a.m - 1);
                 if (t == 0) {
-                    stage<R, K, L, LA, COMP>(a, jin, last_row, last_col, cA, cAl, cB, cBl, cux, cuy, cw, fq[0],
+                    stage<R, K, GK, L, LA, COMP>(a, jin, last_row, last_col, cA, cAl, cB, cBl, cux, cuy, cw, fq[0],
                                              carry[0], phN[0], plN[0], uxN[0], uyN[0], wN[0]);
                 } else {
-                    stage<R, K, L, LA, COMP>(a, jin, last_row, last_col, phP[t - 1], plP[t - 1], phN[t - 1],
+                    stage<R, K, GK, L, LA, COMP>(a, jin, last_row, last_col, phP[t - 1], plP[t - 1], phN[t - 1],
                                              plN[t - 1], uxP[t - 1], uyP[t - 1], wP[t - 1], fq[t], carry[t],
                                              phN[t], plN[t], uxN[t], uyN[t], wN[t]);
                 }
@@ -345,40 +381,44 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step_kernel(cons
     }
 }
 
-template <typename R, int K, int L, int T, bool COMP>
+template <typename R, int GK, int L, int T, bool COMP>
 hipError_t launch_one(const StepLaunch &Lc)
 {
     const StepArgs<R> &a = *static_cast<const StepArgs<R> *>(Lc.args);
-    hipLaunchKernelGGL((pdhg_step_kernel<R, K, L, T, COMP>), dim3(a.nwg), dim3(WAVE * STEP_WAVES_PER_WG), 0,
+    hipLaunchKernelGGL((pdhg_step_kernel<R, OMT_K, GK, L, T, COMP>), dim3(a.nwg), dim3(WAVE * STEP_WAVES_PER_WG), 0,
                        Lc.stream, a);
     return hipGetLastError();
 }
 
-// Blocking depths compiled for this channel count (register budget).
+// Blocking depths compiled for this channel count (register budget); dense
+// graphs and FP64 run one iteration per launch.
 constexpr bool t_ok(int T) { return T == 1 || T == 2 || (T == 4 && OMT_K <= 5) || (T == 8 && OMT_K <= 3); }
 
-template <int L>
+template <int GK, int L>
 hipError_t dispatch_T(const StepLaunch &Lc)
 {
     if (Lc.dtype == 1) {
-        if (Lc.T == 1) return launch_one<double, OMT_K, L, 1, false>(Lc);
+        if (Lc.T == 1 && !Lc.comp) return launch_one<double, GK, L, 1, false>(Lc);
         return hipErrorInvalidValue;
     }
-    switch (Lc.T) {
-        case 1: return Lc.comp ? launch_one<float, OMT_K, L, 1, true>(Lc) : launch_one<float, OMT_K, L, 1, false>(Lc);
-        case 2: return Lc.comp ? launch_one<float, OMT_K, L, 2, true>(Lc) : launch_one<float, OMT_K, L, 2, false>(Lc);
+    if (Lc.T == 1) return Lc.comp ? launch_one<float, GK, L, 1, true>(Lc) : launch_one<float, GK, L, 1, false>(Lc);
+    if constexpr (GK != G_DENSE) {
+        switch (Lc.T) {
+            case 2: return Lc.comp ? launch_one<float, GK, L, 2, true>(Lc) : launch_one<float, GK, L, 2, false>(Lc);
 #if OMT_K <= 5
-        case 4: return Lc.comp ? launch_one<float, OMT_K, L, 4, true>(Lc) : launch_one<float, OMT_K, L, 4, false>(Lc);
+            case 4: return Lc.comp ? launch_one<float, GK, L, 4, true>(Lc) : launch_one<float, GK, L, 4, false>(Lc);
 #endif
 #if OMT_K <= 3
-        case 8: return Lc.comp ? launch_one<float, OMT_K, L, 8, true>(Lc) : launch_one<float, OMT_K, L, 8, false>(Lc);
+            case 8: return Lc.comp ? launch_one<float, GK, L, 8, true>(Lc) : launch_one<float, GK, L, 8, false>(Lc);
 #endif
-        default: return hipErrorInvalidValue;
+            default: break;
+        }
     }
+    return hipErrorInvalidValue;
 }
 
-constexpr int LB_TREE = OMT_K - 1;
-constexpr int LB_FULL = OMT_K * (OMT_K - 1) / 2;
+constexpr int L_TREE = OMT_K - 1;
+constexpr int L_FULL = OMT_K * (OMT_K - 1) / 2;
 
 }  // namespace
 
@@ -387,21 +427,27 @@ constexpr int LB_FULL = OMT_K * (OMT_K - 1) / 2;
 
 hipError_t OMT_CAT(launch_step_k, OMT_K)(const StepLaunch &Lc)
 {
-    if (Lc.lb == 0) return dispatch_T<0>(Lc);
+    if (Lc.gk == G_NONE && Lc.lb == 0) return dispatch_T<G_NONE, 0>(Lc);
 #if OMT_K >= 2
-    if (Lc.lb == LB_TREE) return dispatch_T<LB_TREE>(Lc);
+    if (Lc.gk == G_PATH && Lc.lb == L_TREE) return dispatch_T<G_PATH, L_TREE>(Lc);
 #endif
 #if OMT_K >= 3
-    if (Lc.lb == LB_FULL) return dispatch_T<LB_FULL>(Lc);
+    if (Lc.gk == G_COMPLETE && Lc.lb == L_FULL) return dispatch_T<G_COMPLETE, L_FULL>(Lc);
+    if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return dispatch_T<G_DENSE, L_TREE>(Lc);
+    if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return dispatch_T<G_DENSE, L_FULL>(Lc);
 #endif
     return hipErrorInvalidValue;
 }
 
-bool OMT_CAT(step_supported_k, OMT_K)(int dtype, int lb, int T, bool comp)
+bool OMT_CAT(step_supported_k, OMT_K)(int dtype, int gk, int lb, int T, bool comp)
 {
-    const bool lb_ok = lb == 0 || (OMT_K >= 2 && lb == LB_TREE) || (OMT_K >= 3 && lb == LB_FULL);
-    if (!lb_ok) return false;
+    bool ok = (gk == G_NONE && lb == 0);
+    ok = ok || (OMT_K >= 2 && gk == G_PATH && lb == L_TREE);
+    ok = ok || (OMT_K >= 3 && gk == G_COMPLETE && lb == L_FULL);
+    ok = ok || (OMT_K >= 3 && gk == G_DENSE && (lb == L_TREE || lb == L_FULL));
+    if (!ok) return false;
     if (dtype == 1) return T == 1 && !comp;
+    if (gk == G_DENSE) return T == 1;
     return t_ok(T);
 }
 

@@ -109,10 +109,10 @@ def test_fp64_convergence_check_cadence():
     """Stops at the same check as the oracle and reports the same residual."""
     torch = cuda()
     r0, r1 = I.random_pair(24, 24, 24, 3)
-    note("case: fp64 24x24 to tol 1e-6")
-    r = oracle_run(r0, r1, I.TRIANGLE, 200000, tol=1e-6, check_every=64)
+    note("case: fp64 24x24 to tol 1e-4")
+    r = oracle_run(r0, r1, I.TRIANGLE, 200000, tol=1e-4, check_every=64)
     s = _solver(torch, r0, r1, I.TRIANGLE, "f64")
-    info = s.solve(200000, 1e-6, 64)
+    info = s.solve(200000, 1e-4, 64)
     assert r["converged"] and info["converged"]
     assert info["iters"] == r["iters"]
     assert abs(info["residual"] - r["residual"]) <= 1e-6 * r["residual"]
