@@ -374,11 +374,15 @@ void fill_step_args(StepArgs<R> &a, const omt_ctx *h, int T, int rows, bool w_in
     }
 }
 
+// Output columns of one wavefront: 64 aligned columns at one iteration per
+// launch, 64 - 2T (plus halo lanes) when T iterations are pipelined.
+int strip_cols(int T) { return T == 1 ? WAVE : WAVE - 2 * T; }
+
 int default_rows(const omt_ctx *h, int T)
 {
     if (h->r.rows > 0) return h->r.rows;
     // enough waves to cover the chip (>= ~2 per SIMD), chunks of 4..32 rows
-    const int ncolw = (h->r.n + (WAVE - 2 * T) - 1) / (WAVE - 2 * T);
+    const int ncolw = (h->r.n + strip_cols(T) - 1) / strip_cols(T);
     const int want_waves = 2048;
     int rows = int((int64_t)h->r.m * ncolw / want_waves);
     rows = std::max(rows, 4 * T);
@@ -394,7 +398,7 @@ omt_status step_launch(omt_ctx *h, int T, int rows, bool w_inplace)
         return fail(OMT_EUNSUPPORTED, "no step kernel for dtype %d, k %d, graph kind %d (%d edges), T %d%s", r.dtype,
                     r.k, r.gk, r.lb, T, r.comp ? ", compensated" : "");
     if (T > 1) w_inplace = false;  // halo lanes of a pipelined step must see the old w
-    const int ncolw = (r.n + (WAVE - 2 * T) - 1) / (WAVE - 2 * T);
+    const int ncolw = (r.n + strip_cols(T) - 1) / strip_cols(T);
     const int nroww = (r.m + rows - 1) / rows;
     const int nwg = ncolw * ((nroww + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG);
     StepLaunch Lc;

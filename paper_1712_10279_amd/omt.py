@@ -254,3 +254,51 @@ def distance(rho0, rho1, edges=None, max_iters=10000, tol=0.0, check_every=64, *
     s = Solver(rho0, rho1, edges, **kw)
     s.solve(max_iters, tol, check_every)
     return s.distance()[0]
+
+
+# ----------------------------------------------------------------- autograd
+
+def _autograd_function():
+    torch = _torch()
+
+    class OMTDistance(torch.autograd.Function):
+        """V(rho0, rho1) as a differentiable loss.
+
+        Forward: solve on the GPU (to ``tol`` or for ``max_iters``) and return
+        the transport cost V (the discrete primal objective, App. A).  Backward:
+        dV/drho0 = Phi and dV/drho1 = -Phi, with Phi = -phi minus its mean per
+        mass class (dual problem, Sec. 3.2); no second solve is needed.
+        """
+
+        @staticmethod
+        def forward(ctx, rho0, rho1, edges, max_iters, tol, check_every, kw):
+            s = Solver(rho0.detach(), rho1.detach(), edges, **kw)
+            s.solve(max_iters, tol, check_every)
+            V, info = s.distance()
+            d0, _ = s.grad()
+            ctx.save_for_backward(d0)
+            ctx.info = info
+            return torch.tensor(V, dtype=rho0.dtype, device=rho0.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            (d0,) = ctx.saved_tensors
+            return g * d0, -g * d0, None, None, None, None, None
+
+    return OMTDistance
+
+
+_OMT_FN = None
+
+
+def omt_loss(rho0, rho1, edges=None, max_iters=100000, tol=1e-6, check_every=64, **kw):
+    """Differentiable V(rho0, rho1) (see ``OMTDistance``); rho0 / rho1 may be
+    (m, n, k) or a batch (B, m, n, k), which returns a (B,) tensor."""
+    global _OMT_FN
+    if _OMT_FN is None:
+        _OMT_FN = _autograd_function()
+    if rho0.dim() == 4:
+        torch = _torch()
+        return torch.stack([_OMT_FN.apply(rho0[b], rho1[b], edges, max_iters, tol, check_every, kw)
+                            for b in range(rho0.shape[0])])
+    return _OMT_FN.apply(rho0, rho1, edges, max_iters, tol, check_every, kw)
