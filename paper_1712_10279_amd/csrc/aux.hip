@@ -1,7 +1,7 @@
 // Set-up, reduction and layout kernels around the fused PDHG step: FP64
 // sums of the input densities (mass check), the source term f, the
-// per-check metrics (fixed-point residual of Sec. 6.1, primal and dual
-// objectives, constraint residual), the exported potential and the
+// reductions of the per-check metrics (computed in metrics_device.h), the
+// exported potential and the
 // conversions between the caller's layout (m x n x k, channel fastest) and
 // the SoA planes the step kernel streams.
 //
@@ -9,7 +9,7 @@
 // shuffles, then LDS, in a fixed order) and a single-workgroup kernel sums
 // the rows in a fixed order, so results are deterministic.
 
-#include "omt_kernels.h"
+#include "metrics_device.h"
 
 namespace omt {
 namespace {
@@ -110,84 +110,7 @@ __global__ void make_f_kernel(MakeFArgs a)
     }
 }
 
-// ---------------------------------------------------------------- metrics
-
-template <typename R>
-__global__ __launch_bounds__(RB) void metrics_kernel(MetricArgs a)
-{
-    const R *phi0 = static_cast<const R *>(a.phi0), *phi1 = static_cast<const R *>(a.phi1);
-    const R *u0 = static_cast<const R *>(a.u0), *u1 = static_cast<const R *>(a.u1);
-    const R *w0 = static_cast<const R *>(a.w0), *w1 = static_cast<const R *>(a.w1);
-    const R *f = static_cast<const R *>(a.f);
-    const int64_t P = a.plane;
-    const int k = a.k, l = a.l;
-    double v[NMET];
-#pragma unroll
-    for (int q = 0; q < NMET; ++q) v[q] = 0.0;
-
-    for (int64_t p = blockIdx.x * (int64_t)RB + threadIdx.x; p < (int64_t)a.m * a.n; p += (int64_t)a.nblocks * RB) {
-        const int i = int(p / a.n), j = int(p % a.n);
-        const int64_t o = (int64_t)i * a.pitch + j;
-        const int64_t oi = o - a.pitch, oj = o - 1;
-        double u2 = 0.0, w2 = 0.0;
-        for (int c = 0; c < k; ++c) {
-            double p0 = double(phi0[c * P + o]), p1 = double(phi1[c * P + o]);
-            if (a.plo0) {
-                p0 += double(a.plo0[c * P + o]);
-                p1 += double(a.plo1[c * P + o]);
-            }
-            const double dp = p1 - p0;
-            const double ux0 = i < a.m - 1 ? double(u0[c * P + o]) : 0.0;
-            const double ux1 = i < a.m - 1 ? double(u1[c * P + o]) : 0.0;
-            const double uy0 = j < a.n - 1 ? double(u0[(k + c) * P + o]) : 0.0;
-            const double uy1 = j < a.n - 1 ? double(u1[(k + c) * P + o]) : 0.0;
-            const double xl0 = i > 0 ? double(u0[c * P + oi]) : 0.0;
-            const double xl1 = i > 0 ? double(u1[c * P + oi]) : 0.0;
-            const double yl0 = j > 0 ? double(u0[(k + c) * P + oj]) : 0.0;
-            const double yl1 = j > 0 ? double(u1[(k + c) * P + oj]) : 0.0;
-            const double dux = ux1 - ux0, duy = uy1 - uy0;
-            const double ddiv = ((dux - (xl1 - xl0)) + duy - (yl1 - yl0)) * a.inv_h;
-            const double div1 = ((ux1 - xl1) + uy1 - yl1) * a.inv_h;
-            double dgd = 0.0, dg1 = 0.0;
-            for (int e = 0; e < l; ++e) {
-                const double we0 = double(w0[e * P + o]), we1 = double(w1[e * P + o]);
-                dgd += a.gm[c * LMAX + e] * (we1 - we0);
-                dg1 += a.gm[c * LMAX + e] * we1;
-            }
-            const double fc = double(f[c * P + o]);
-            v[0] += dux * dux + duy * duy;
-            v[2] += dp * dp;
-            v[3] += dp * (ddiv - dgd);
-            v[5] += p1 * fc;
-            const double r = (div1 - dg1) + fc;
-            v[6] += r * r;
-            v[7] += p1;
-            if (a.unorm == 0)
-                v[4] += sqrt(ux1 * ux1 + uy1 * uy1);
-            else if (a.unorm == 1)
-                v[4] += fabs(ux1) + fabs(uy1);
-            else
-                u2 += ux1 * ux1 + uy1 * uy1;
-        }
-        if (a.unorm == 2) v[4] += sqrt(u2);
-        double wn = 0.0;
-        for (int e = 0; e < l; ++e) {
-            const double we0 = double(w0[e * P + o]), we1 = double(w1[e * P + o]);
-            v[1] += (we1 - we0) * (we1 - we0);
-            if (a.wnorm == 0)
-                wn += fabs(we1);
-            else
-                w2 += we1 * we1;
-        }
-        if (a.wnorm == 1) wn = sqrt(w2);
-        v[4] += a.alpha * wn;
-    }
-    double out[NMET];
-    block_sum<NMET>(v, out);
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < NMET; ++q) a.partials[(int64_t)blockIdx.x * NMET + q] = out[q];
-    }
-}
+// ---------------------------------------------------------------- reductions
 
 __global__ __launch_bounds__(RB) void reduce_rows_kernel(const double *partials, int nblocks, int width, double *out)
 {
@@ -204,6 +127,11 @@ __global__ __launch_bounds__(RB) void reduce_rows_kernel(const double *partials,
         if (threadIdx.x == 0) out[q] = sm[0];
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(WAVE) void reduce_tiles_kernel(const double *partials, int ntiles, double *out)
+{
+    dev::reduce_tiles(partials, 0, ntiles, threadIdx.x, out);
 }
 
 __global__ __launch_bounds__(RB) void plane_sums_kernel(PlaneSumArgs a)
@@ -289,18 +217,15 @@ hipError_t launch_make_f(const MakeFArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_metrics(const MetricArgs &a, hipStream_t s)
-{
-    if (a.dtype == 1)
-        hipLaunchKernelGGL(metrics_kernel<double>, dim3(a.nblocks), dim3(RB), 0, s, a);
-    else
-        hipLaunchKernelGGL(metrics_kernel<float>, dim3(a.nblocks), dim3(RB), 0, s, a);
-    return hipGetLastError();
-}
-
 hipError_t launch_reduce_rows(const double *partials, int nblocks, int width, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(RB), 0, s, partials, nblocks, width, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_tiles(const double *partials, int ntiles, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_tiles_kernel, dim3(1), dim3(WAVE), 0, s, partials, ntiles, out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,187 @@
+// Persistent batched PDHG solver: many independent problems (different grid
+// sizes, channel counts and graphs) iterated together by one launch.
+//
+// The grid is sized to the number of workgroups the chip holds at once, so
+// every workgroup is resident, and it stays for the whole solve.  Each
+// iteration the waves walk the list of strips (64 columns x rows) of all
+// unfinished problems, run the same per-strip code as the per-launch step
+// kernel, and meet at a grid barrier.  At a check iteration they compute the
+// metrics tiles, meet, let one wave per problem reduce its tiles and decide
+// whether the problem has converged (it then drops out of the strip list),
+// and meet again.  The barrier's wait is bounded: if it ever expires every
+// wave sees the abort flag and leaves, and the host reports the error.
+//
+// Supported problem types (compiled in): k = 1 without edges, k = 2 with one
+// edge, k = 3 on the complete graph (triangle) or on the path; FP32 with or
+// without the compensated potential; one iteration per pass.
+
+#include "metrics_device.h"
+
+namespace omt {
+namespace {
+
+using namespace dev;
+
+constexpr unsigned SPIN_LIMIT = 1u << 25;  // ~ seconds of s_sleep before a barrier gives up
+
+__device__ __forceinline__ unsigned ld_acq(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier over nblocks resident workgroups: bar[0] arrivals,
+// bar[1] generation, bar[2] abort flag.  Returns true if the barrier was
+// abandoned (abort flag set).
+__device__ bool grid_sync(unsigned *bar, unsigned nblocks)
+{
+    __shared__ int s_abort;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned gen = ld_acq(&bar[1]);
+        const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (arrived == nblocks) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (ld_acq(&bar[1]) == gen) {
+                if (ld_acq(&bar[2]) != 0u) break;
+                if (++spins > SPIN_LIMIT) {
+                    __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        s_abort = int(ld_acq(&bar[2]));
+    }
+    __syncthreads();
+    __threadfence();
+    return s_abort != 0;
+}
+
+template <bool COMP>
+__device__ __forceinline__ void strip_by_type(int type, const StepArgs<float> &a, int wc, int wr, int lane)
+{
+    switch (type) {
+        case 0: process_strip<float, 1, G_NONE, 0, 1, COMP>(a, wc, wr, lane); break;
+        case 1: process_strip<float, 2, G_PATH, 1, 1, COMP>(a, wc, wr, lane); break;
+        case 2: process_strip<float, 3, G_COMPLETE, 3, 1, COMP>(a, wc, wr, lane); break;
+        case 3: process_strip<float, 3, G_PATH, 2, 1, COMP>(a, wc, wr, lane); break;
+        default: break;
+    }
+}
+
+template <bool COMP>
+__device__ __forceinline__ void metrics_by_type(int type, const StepArgs<float> &a, int wc, int wr, int lane,
+                                                double (&v)[NMET])
+{
+    switch (type) {
+        case 0: tile_metrics<float, 1, G_NONE, 0, COMP>(a, wc, wr, lane, v); break;
+        case 1: tile_metrics<float, 2, G_PATH, 1, COMP>(a, wc, wr, lane, v); break;
+        case 2: tile_metrics<float, 3, G_COMPLETE, 3, COMP>(a, wc, wr, lane, v); break;
+        case 3: tile_metrics<float, 3, G_PATH, 2, COMP>(a, wc, wr, lane, v); break;
+        default:
+            for (int q = 0; q < NMET; ++q) v[q] = 0.0;
+            break;
+    }
+}
+
+template <bool COMP>
+__global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_kernel(const BatchArgs ba)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int nw = gridDim.x * STEP_WAVES_PER_WG;
+    const int gw = blockIdx.x * STEP_WAVES_PER_WG + threadIdx.x / WAVE;
+    const unsigned nblocks = gridDim.x;
+    int nchecks = 0;
+    for (int64_t it = 0; it < ba.max_iters; ++it) {
+        const bool check = ((it + 1) % ba.check_every == 0) || (it + 1 == ba.max_iters);
+        const int par = int(it & 1);
+        const int wcur = nchecks & 1;
+        const int var = par * 4 + wcur * 2 + (check ? 1 : 0);
+
+        // one iteration of every unfinished problem
+        for (int t = gw; t < ba.total_tiles; t += nw) {
+            const int p = __builtin_amdgcn_readfirstlane(ba.tile_pair[t]);
+            if (__hip_atomic_load(&ba.state[p].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
+            const BatchPair &bp = ba.pairs[p];
+            const int local = t - bp.tile0;
+            strip_by_type<COMP>(bp.type, bp.v[var], local % bp.ncolw, local / bp.ncolw, lane);
+        }
+        if (grid_sync(ba.bar, nblocks)) return;
+        if (!check) continue;
+
+        // metrics of the step just taken, tile by tile
+        for (int t = gw; t < ba.total_mtiles; t += nw) {
+            const int p = __builtin_amdgcn_readfirstlane(ba.mtile_pair[t]);
+            if (__hip_atomic_load(&ba.state[p].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
+            const BatchPair &bp = ba.pairs[p];
+            const int local = t - bp.mtile0;
+            double v[NMET];
+            metrics_by_type<COMP>(bp.type, bp.v[var], local % bp.mcolw, local / bp.mcolw, lane, v);
+#pragma unroll
+            for (int q = 0; q < NMET; ++q) {
+                const double s = wave_sum(v[q]);
+                if (lane == 0) ba.partials[(int64_t)t * NMET + q] = s;
+            }
+        }
+        if (grid_sync(ba.bar, nblocks)) return;
+
+        // per problem: reduce its tiles and take the stopping decision
+        for (int p = gw; p < ba.B; p += nw) {
+            BatchPairState &st = ba.state[p];
+            if (__hip_atomic_load(&st.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
+            const BatchPair &bp = ba.pairs[p];
+            reduce_tiles(ba.partials, bp.mtile0, bp.mtiles, lane, st.met);
+            if (lane == 0) {
+                const double *m = st.met;
+                const double R = m[0] / bp.mu + (bp.l > 0 ? m[1] / bp.nu : 0.0) + m[2] / bp.tau - 2.0 * m[3];
+                const bool conv = ba.tol > 0.0 && R <= ba.tol * ba.tol * bp.R0;
+                const bool bad = !isfinite(R) || !isfinite(m[4]);
+                st.iters = it + 1;
+                st.checks = nchecks + 1;
+                st.cur = 1 - par;
+                st.wcur = 1 - wcur;
+                if (conv || bad || it + 1 == ba.max_iters) {
+                    st.converged = conv ? 1 : 0;
+                    __hip_atomic_store(&st.done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&ba.bar[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+        if (grid_sync(ba.bar, nblocks)) return;
+        ++nchecks;
+        if (ld_acq(&ba.bar[3]) >= unsigned(ba.B)) break;  // every problem has stopped
+    }
+}
+
+}  // namespace
+
+int batch_type(int k, int gk, int lb)
+{
+    if (k == 1 && gk == G_NONE && lb == 0) return 0;
+    if (k == 2 && gk == G_PATH && lb == 1) return 1;
+    if (k == 3 && gk == G_COMPLETE && lb == 3) return 2;
+    if (k == 3 && gk == G_PATH && lb == 2) return 3;
+    return -1;
+}
+
+hipError_t batch_blocks_per_cu(bool comp, int *blocks)
+{
+    if (comp)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, batch_kernel<true>, WAVE * STEP_WAVES_PER_WG, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, batch_kernel<false>, WAVE * STEP_WAVES_PER_WG, 0);
+}
+
+hipError_t launch_batch(const BatchArgs &a, bool comp, int nblocks, hipStream_t s)
+{
+    if (comp)
+        hipLaunchKernelGGL(batch_kernel<true>, dim3(nblocks), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a);
+    else
+        hipLaunchKernelGGL(batch_kernel<false>, dim3(nblocks), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace omt

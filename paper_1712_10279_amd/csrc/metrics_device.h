@@ -1,0 +1,135 @@
+// Device code of the check-iteration metrics, shared by the per-problem
+// solve and the persistent batched kernel so that both take identical
+// stopping decisions.
+//
+// For one step (u, w, phi) -> (u', w', phi') every pixel contributes, in
+// FP64 (Sec. 6.1 fixed-point residual with 1/nu on the w block, App. A
+// objectives):
+//   v[0] = |u' - u|^2             v[1] = |w' - w|^2        v[2] = |phi' - phi|^2
+//   v[3] = <phi' - phi, div_x(u' - u) + div_G(w' - w)>
+//   v[4] = ||u'||_u + alpha ||w'||_w                        (primal objective)
+//   v[5] = <phi', f>                                         (dual objective)
+//   v[6] = |div_x u' + div_G w' + f|^2                       (constraint residual)
+//   v[7] = sum of phi'
+// A tile is 64 aligned columns by MET_ROWS rows; each wave sums one tile and
+// a single wave adds the tiles of a problem in tile order.
+#pragma once
+
+#include "step_device.h"
+
+namespace omt {
+namespace dev {
+
+constexpr int MET_ROWS = 16;
+
+template <typename R, int K, int GK, int L, bool COMP>
+__device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int wr, int lane, double (&v)[NMET])
+{
+    constexpr int LA = L > 0 ? L : 1;
+#pragma unroll
+    for (int q = 0; q < NMET; ++q) v[q] = 0.0;
+    const int j = wc * WAVE + lane;
+    if (j >= a.n) return;
+    const int i0 = wr * MET_ROWS, i1 = min(i0 + MET_ROWS, a.m);
+    const int64_t P = a.plane;
+    const R *phi0 = a.phi_in, *phi1 = a.phi_out, *u0 = a.u_in, *u1 = a.u_out, *w0 = a.w_in, *w1 = a.w_out;
+    const double inv_h = double(a.inv_h);
+    for (int i = i0; i < i1; ++i) {
+        const int64_t o = (int64_t)i * a.pitch + j;
+        const int64_t oi = o - a.pitch, oj = o - 1;
+        double we0[LA], we1[LA];
+#pragma unroll
+        for (int e = 0; e < LA; ++e) {
+            const bool on = L > 0 && e < a.l;
+            we0[e] = on ? double(w0[e * P + o]) : 0.0;
+            we1[e] = on ? double(w1[e * P + o]) : 0.0;
+        }
+        double u2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            double p0 = double(phi0[c * P + o]), p1 = double(phi1[c * P + o]);
+            if (COMP) {
+                p0 += double(a.plo_in[c * P + o]);
+                p1 += double(a.plo_out[c * P + o]);
+            }
+            const double dp = p1 - p0;
+            const double ux0 = i < a.m - 1 ? double(u0[c * P + o]) : 0.0;
+            const double ux1 = i < a.m - 1 ? double(u1[c * P + o]) : 0.0;
+            const double uy0 = j < a.n - 1 ? double(u0[(K + c) * P + o]) : 0.0;
+            const double uy1 = j < a.n - 1 ? double(u1[(K + c) * P + o]) : 0.0;
+            const double xl0 = i > 0 ? double(u0[c * P + oi]) : 0.0;
+            const double xl1 = i > 0 ? double(u1[c * P + oi]) : 0.0;
+            const double yl0 = j > 0 ? double(u0[(K + c) * P + oj]) : 0.0;
+            const double yl1 = j > 0 ? double(u1[(K + c) * P + oj]) : 0.0;
+            const double dux = ux1 - ux0, duy = uy1 - uy0;
+            const double ddiv = ((dux - (xl1 - xl0)) + duy - (yl1 - yl0)) * inv_h;
+            const double div1 = ((ux1 - xl1) + uy1 - yl1) * inv_h;
+            // D diag(1/c) applied to w' - w and to w' (div_G is its negative)
+            double dgd = 0.0, dg1 = 0.0;
+            if constexpr (L > 0) {
+#pragma unroll
+                for (int e = 0; e < LA; ++e) {
+                    if constexpr (GK == G_DENSE) {
+                        dgd += double(a.gm[c * LMAX + e]) * (we1[e] - we0[e]);
+                        dg1 += double(a.gm[c * LMAX + e]) * we1[e];
+                    } else {
+                        if (edge_a<GK, K>(e) == c) {
+                            dgd += double(a.ic[e]) * (we1[e] - we0[e]);
+                            dg1 += double(a.ic[e]) * we1[e];
+                        }
+                        if (edge_b<GK, K>(e) == c) {
+                            dgd -= double(a.ic[e]) * (we1[e] - we0[e]);
+                            dg1 -= double(a.ic[e]) * we1[e];
+                        }
+                    }
+                }
+            }
+            const double fc = double(a.f[c * P + o]);
+            v[0] += dux * dux + duy * duy;
+            v[2] += dp * dp;
+            v[3] += dp * (ddiv - dgd);
+            v[5] += p1 * fc;
+            const double r = (div1 - dg1) + fc;
+            v[6] += r * r;
+            v[7] += p1;
+            if (a.unorm == 0)
+                v[4] += sqrt(ux1 * ux1 + uy1 * uy1);
+            else if (a.unorm == 1)
+                v[4] += fabs(ux1) + fabs(uy1);
+            else
+                u2 += ux1 * ux1 + uy1 * uy1;
+        }
+        if (a.unorm == 2) v[4] += sqrt(u2);
+        double wn = 0.0, w2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < LA; ++e) {
+            v[1] += (we1[e] - we0[e]) * (we1[e] - we0[e]);
+            wn += fabs(we1[e]);
+            w2 += we1[e] * we1[e];
+        }
+        v[4] += a.alpha * (a.wnorm == 0 ? wn : sqrt(w2));
+    }
+}
+
+// Sum over the 64 lanes of a wave (fixed tree); lane 0 holds the result.
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) x += __shfl_down(x, off, WAVE);
+    return x;
+}
+
+// One wave: out[q] = sum over tiles t0..t0+nt-1 of partials[t][q], in a fixed
+// order (lane l takes tiles l, l+64, ...; then the wave tree).
+__device__ __forceinline__ void reduce_tiles(const double *partials, int t0, int nt, int lane, double *out)
+{
+    for (int q = 0; q < NMET; ++q) {
+        double s = 0.0;
+        for (int t = lane; t < nt; t += WAVE) s += partials[(int64_t)(t0 + t) * NMET + q];
+        s = wave_sum(s);
+        if (lane == 0) out[q] = s;
+    }
+}
+
+}  // namespace dev
+}  // namespace omt

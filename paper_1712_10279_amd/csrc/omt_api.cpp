@@ -28,6 +28,14 @@ hipError_t launch_step_k5(const StepLaunch &);
 hipError_t launch_step_k6(const StepLaunch &);
 hipError_t launch_step_k7(const StepLaunch &);
 hipError_t launch_step_k8(const StepLaunch &);
+hipError_t launch_metrics_k1(const StepLaunch &, int, int, double *);
+hipError_t launch_metrics_k2(const StepLaunch &, int, int, double *);
+hipError_t launch_metrics_k3(const StepLaunch &, int, int, double *);
+hipError_t launch_metrics_k4(const StepLaunch &, int, int, double *);
+hipError_t launch_metrics_k5(const StepLaunch &, int, int, double *);
+hipError_t launch_metrics_k6(const StepLaunch &, int, int, double *);
+hipError_t launch_metrics_k7(const StepLaunch &, int, int, double *);
+hipError_t launch_metrics_k8(const StepLaunch &, int, int, double *);
 bool step_supported_k1(int, int, int, int, bool);
 bool step_supported_k2(int, int, int, int, bool);
 bool step_supported_k3(int, int, int, int, bool);
@@ -48,6 +56,21 @@ hipError_t launch_step(const StepLaunch &L)
         case 6: return launch_step_k6(L);
         case 7: return launch_step_k7(L);
         case 8: return launch_step_k8(L);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_tile_metrics(const StepLaunch &L, int ncolw, int ntiles, double *partials)
+{
+    switch (L.k) {
+        case 1: return launch_metrics_k1(L, ncolw, ntiles, partials);
+        case 2: return launch_metrics_k2(L, ncolw, ntiles, partials);
+        case 3: return launch_metrics_k3(L, ncolw, ntiles, partials);
+        case 4: return launch_metrics_k4(L, ncolw, ntiles, partials);
+        case 5: return launch_metrics_k5(L, ncolw, ntiles, partials);
+        case 6: return launch_metrics_k6(L, ncolw, ntiles, partials);
+        case 7: return launch_metrics_k7(L, ncolw, ntiles, partials);
+        case 8: return launch_metrics_k8(L, ncolw, ntiles, partials);
         default: return hipErrorInvalidValue;
     }
 }
@@ -300,7 +323,10 @@ Layout make_layout(const Resolved &r)
         o += r.comp ? pf * r.k : 0;
     }
     L.off_part = o;
-    o += align256(sizeof(double) * size_t(std::max(METRIC_BLOCKS_MAX * NMET, SUM_BLOCKS_MAX * (4 * KMAX + 1))));
+    const size_t met_tiles = size_t((r.n + WAVE - 1) / WAVE) * size_t((r.m + 15) / 16);
+    size_t npart = std::max<size_t>(size_t(METRIC_BLOCKS_MAX) * KMAX, size_t(SUM_BLOCKS_MAX) * (4 * KMAX + 1));
+    npart = std::max(npart, met_tiles * NMET);
+    o += align256(sizeof(double) * npart);
     L.off_res = o;
     o += align256(sizeof(double) * 64);
     L.off_vec = o;
@@ -333,18 +359,19 @@ struct omt_ctx {
 
 namespace {
 
+// Step arguments reading buffers (ci, wi) and writing buffers (co, wo).
 template <typename R>
-void fill_step_args(StepArgs<R> &a, const omt_ctx *h, int T, int rows, bool w_inplace, int ncolw, int nroww,
-                    int nwg)
+void fill_args(StepArgs<R> &a, const omt_ctx *h, int ci, int co, int wi, int wo, int rows, int ncolw, int nroww,
+               int nwg)
 {
     const Resolved &r = h->r;
-    const int nc = h->cur, nx = 1 - h->cur;
+    const int nc = ci, nx = co;
     a.phi_in = static_cast<const R *>(h->phi[nc]);
     a.phi_out = static_cast<R *>(h->phi[nx]);
     a.u_in = static_cast<const R *>(h->u[nc]);
     a.u_out = static_cast<R *>(h->u[nx]);
-    a.w_in = static_cast<const R *>(h->w[h->wcur]);
-    a.w_out = static_cast<R *>(h->w[w_inplace ? h->wcur : 1 - h->wcur]);
+    a.w_in = static_cast<const R *>(h->w[wi]);
+    a.w_out = static_cast<R *>(h->w[wo]);
     a.f = static_cast<const R *>(h->f);
     a.plo_in = r.comp ? h->plo[nc] : nullptr;
     a.plo_out = r.comp ? h->plo[nx] : nullptr;
@@ -365,6 +392,7 @@ void fill_step_args(StepArgs<R> &a, const omt_ctx *h, int T, int rows, bool w_in
     a.anu = R(r.alpha * r.nu);
     a.tau = R(r.tau);
     a.inv_h = R(1.0 / r.h);
+    a.alpha = r.alpha;
     for (int q = 0; q < KMAX * LMAX; ++q) a.gm[q] = R(0);
     for (int q = 0; q < LMAX; ++q) a.ic[q] = R(0);
     for (int e = 0; e < r.l; ++e) {
@@ -410,14 +438,15 @@ omt_status step_launch(omt_ctx *h, int T, int rows, bool w_inplace)
     Lc.comp = r.comp;
     Lc.stream = h->stream;
     hipError_t e;
+    const int wo = w_inplace ? h->wcur : 1 - h->wcur;
     if (r.dtype == OMT_F64) {
         StepArgs<double> a;
-        fill_step_args(a, h, T, rows, w_inplace, ncolw, nroww, nwg);
+        fill_args(a, h, h->cur, 1 - h->cur, h->wcur, wo, rows, ncolw, nroww, nwg);
         Lc.args = &a;
         e = launch_step(Lc);
     } else {
         StepArgs<float> a;
-        fill_step_args(a, h, T, rows, w_inplace, ncolw, nroww, nwg);
+        fill_args(a, h, h->cur, 1 - h->cur, h->wcur, wo, rows, ncolw, nroww, nwg);
         Lc.args = &a;
         e = launch_step(Lc);
     }
@@ -432,36 +461,30 @@ omt_status step_launch(omt_ctx *h, int T, int rows, bool w_inplace)
 omt_status run_metrics(omt_ctx *h, int old_c, int new_c, int old_w, int new_w)
 {
     const Resolved &r = h->r;
-    MetricArgs a;
-    a.phi0 = h->phi[old_c];
-    a.phi1 = h->phi[new_c];
-    a.u0 = h->u[old_c];
-    a.u1 = h->u[new_c];
-    a.w0 = h->w[old_w];
-    a.w1 = h->w[new_w];
-    a.f = h->f;
-    a.plo0 = r.comp ? h->plo[old_c] : nullptr;
-    a.plo1 = r.comp ? h->plo[new_c] : nullptr;
-    a.dtype = r.dtype;
-    a.m = r.m;
-    a.n = r.n;
-    a.k = r.k;
-    a.l = r.l;
-    a.pitch = h->L.pitch;
-    a.plane = h->L.plane;
-    a.unorm = r.unorm;
-    a.wnorm = r.wnorm;
-    a.inv_h = 1.0 / r.h;
-    a.alpha = r.alpha;
-    for (int q = 0; q < KMAX * LMAX; ++q) a.gm[q] = 0.0;
-    for (int e = 0; e < r.l; ++e) {
-        a.gm[r.edges[2 * e] * LMAX + e] = 1.0 / r.cost[e];
-        a.gm[r.edges[2 * e + 1] * LMAX + e] = -1.0 / r.cost[e];
+    const int ncolw = (r.n + WAVE - 1) / WAVE;
+    const int ntiles = ncolw * ((r.m + 15) / 16);
+    StepLaunch Lc;
+    Lc.dtype = r.dtype;
+    Lc.k = r.k;
+    Lc.gk = r.gk;
+    Lc.lb = r.lb;
+    Lc.T = 1;
+    Lc.comp = r.comp;
+    Lc.stream = h->stream;
+    hipError_t e;
+    if (r.dtype == OMT_F64) {
+        StepArgs<double> a;
+        fill_args(a, h, old_c, new_c, old_w, new_w, 16, ncolw, 0, 0);
+        Lc.args = &a;
+        e = launch_tile_metrics(Lc, ncolw, ntiles, h->part);
+    } else {
+        StepArgs<float> a;
+        fill_args(a, h, old_c, new_c, old_w, new_w, 16, ncolw, 0, 0);
+        Lc.args = &a;
+        e = launch_tile_metrics(Lc, ncolw, ntiles, h->part);
     }
-    a.partials = h->part;
-    a.nblocks = h->metric_blocks;
-    HIP_TRY(launch_metrics(a, h->stream));
-    HIP_TRY(launch_reduce_rows(h->part, a.nblocks, NMET, h->res, h->stream));
+    if (e != hipSuccess) return fail(OMT_EDEVICE, "metrics launch: %s", hipGetErrorString(e));
+    HIP_TRY(launch_reduce_tiles(h->part, ntiles, h->res, h->stream));
     return OMT_OK;
 }
 
@@ -672,7 +695,8 @@ omt_status omt_solve(omt_handle h, int64_t max_iters, double tol, int32_t check_
             if (info) *info = inf;
             return fail(OMT_EDIVERGED, "non-finite residual after %lld iterations", (long long)it);
         }
-        if (tol > 0.0 && inf.residual <= tol) {
+        // same test as the batched kernel: R <= tol^2 R0
+        if (tol > 0.0 && inf.R <= tol * tol * (h->r.tau * h->fnorm2)) {
             inf.converged = 1;
             break;
         }
@@ -868,29 +892,308 @@ omt_status omt_autotune(omt_handle, int32_t, int32_t *, int32_t *, double *)
     return fail(OMT_EUNSUPPORTED, "autotune not built yet");
 }
 
-omt_status omt_batch_workspace_bytes(int32_t, const omt_params *, size_t *)
+}  // extern "C"
+
+// ================================================================ batched
+
+struct omt_bctx {
+    int B;
+    std::vector<omt_ctx *> ctx;
+    hipStream_t stream;  // caller's stream
+    hipStream_t cap;     // private stream the solve graph is captured and replayed on
+    char *ws;
+    BatchPair *d_pairs;
+    BatchPairState *d_state;
+    int *d_tile_pair, *d_mtile_pair;
+    double *d_partials;
+    unsigned *d_bar;
+    int total_tiles, total_mtiles;
+    bool comp;
+    int nblocks;
+    std::vector<BatchPair> pairs;
+    std::vector<BatchPairState> st;
+};
+
+namespace {
+
+constexpr int BATCH_ROWS_DEFAULT = 8;
+
+struct BatchLayout {
+    std::vector<size_t> off, bytes;
+    std::vector<int> ntiles, mtiles, rows;
+    size_t off_pairs, off_state, off_tp, off_mtp, off_part, off_bar, total;
+    int total_tiles, total_mtiles;
+};
+
+omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, bool *comp)
 {
-    return fail(OMT_EUNSUPPORTED, "batched mode not built yet");
+    if (B < 1) return fail(OMT_EINVAL, "batch size %d < 1", B);
+    if (!params) return fail(OMT_EINVAL, "params is NULL");
+    size_t o = 0;
+    L.total_tiles = L.total_mtiles = 0;
+    for (int p = 0; p < B; ++p) {
+        Resolved r;
+        omt_status s = resolve(&params[p], r);
+        if (s != OMT_OK) return fail(s, "problem %d: %s", p, g_last_error.c_str());
+        if (r.dtype != OMT_F32) return fail(OMT_EUNSUPPORTED, "problem %d: the batched kernel runs FP32 only", p);
+        if (batch_type(r.k, r.gk, r.lb) < 0)
+            return fail(OMT_EUNSUPPORTED, "problem %d: k = %d with this graph is not compiled into the batched kernel",
+                        p, r.k);
+        if (p == 0) *comp = r.comp;
+        if (r.comp != *comp) return fail(OMT_EINVAL, "problem %d: all problems must share the compensated flag", p);
+        const size_t b = make_layout(r).total;
+        L.off.push_back(o);
+        L.bytes.push_back(b);
+        o += align256(b);
+        const int rows = r.rows > 0 ? r.rows : BATCH_ROWS_DEFAULT;
+        const int ncolw = (r.n + WAVE - 1) / WAVE;
+        L.rows.push_back(rows);
+        L.ntiles.push_back(ncolw * ((r.m + rows - 1) / rows));
+        L.mtiles.push_back(ncolw * ((r.m + 15) / 16));
+        L.total_tiles += L.ntiles.back();
+        L.total_mtiles += L.mtiles.back();
+    }
+    L.off_pairs = o;
+    o += align256(sizeof(BatchPair) * B);
+    L.off_state = o;
+    o += align256(sizeof(BatchPairState) * B);
+    L.off_tp = o;
+    o += align256(sizeof(int) * L.total_tiles);
+    L.off_mtp = o;
+    o += align256(sizeof(int) * L.total_mtiles);
+    L.off_part = o;
+    o += align256(sizeof(double) * NMET * size_t(L.total_mtiles));
+    L.off_bar = o;
+    o += 256;
+    L.total = o;
+    return OMT_OK;
 }
-omt_status omt_batch_create(int32_t, const omt_params *, const void *const *, const void *const *, void *, size_t,
-                            void *, omt_batch_handle *)
+
+void destroy_batch(omt_bctx *h)
 {
-    return fail(OMT_EUNSUPPORTED, "batched mode not built yet");
+    for (omt_ctx *c : h->ctx) omt_destroy(c);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    delete h;
 }
-omt_status omt_batch_solve(omt_batch_handle, int64_t, double, int32_t, omt_info *)
+
+}  // namespace
+
+extern "C" {
+
+omt_status omt_batch_workspace_bytes(int32_t B, const omt_params *params, size_t *bytes)
 {
-    return fail(OMT_EUNSUPPORTED, "batched mode not built yet");
+    if (!bytes) return fail(OMT_EINVAL, "bytes is NULL");
+    BatchLayout L;
+    bool comp = false;
+    omt_status s = batch_layout(B, params, L, &comp);
+    if (s != OMT_OK) return s;
+    *bytes = L.total;
+    return OMT_OK;
 }
-omt_status omt_batch_distance(omt_batch_handle, double *) { return fail(OMT_EUNSUPPORTED, "batched mode not built yet"); }
-omt_status omt_batch_grad(omt_batch_handle, void *const *, void *const *)
+
+omt_status omt_batch_create(int32_t B, const omt_params *params, const void *const *rho0, const void *const *rho1,
+                            void *workspace, size_t ws_bytes, void *stream, omt_batch_handle *out)
 {
-    return fail(OMT_EUNSUPPORTED, "batched mode not built yet");
+    if (!out) return fail(OMT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!rho0 || !rho1) return fail(OMT_EINVAL, "rho0 / rho1 is NULL");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(OMT_EINVAL, "workspace missing or not 256-byte aligned");
+    BatchLayout L;
+    bool comp = false;
+    omt_status s = batch_layout(B, params, L, &comp);
+    if (s != OMT_OK) return s;
+    if (ws_bytes < L.total) return fail(OMT_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
+
+    omt_bctx *h = new omt_bctx();
+    h->B = B;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->ws = static_cast<char *>(workspace);
+    h->comp = comp;
+    h->total_tiles = L.total_tiles;
+    h->total_mtiles = L.total_mtiles;
+    h->d_pairs = reinterpret_cast<BatchPair *>(h->ws + L.off_pairs);
+    h->d_state = reinterpret_cast<BatchPairState *>(h->ws + L.off_state);
+    h->d_tile_pair = reinterpret_cast<int *>(h->ws + L.off_tp);
+    h->d_mtile_pair = reinterpret_cast<int *>(h->ws + L.off_mtp);
+    h->d_partials = reinterpret_cast<double *>(h->ws + L.off_part);
+    h->d_bar = reinterpret_cast<unsigned *>(h->ws + L.off_bar);
+    for (int p = 0; p < B; ++p) {
+        omt_ctx *c = nullptr;
+        s = omt_create(&params[p], rho0[p], rho1[p], h->ws + L.off[p], L.bytes[p], stream, &c);
+        if (s != OMT_OK) {
+            std::string why = g_last_error;
+            destroy_batch(h);
+            return fail(s, "problem %d: %s", p, why.c_str());
+        }
+        h->ctx.push_back(c);
+    }
+    // problem descriptors and the strip / tile lists
+    std::vector<int> tp, mtp;
+    h->pairs.resize(B);
+    int t0 = 0, m0 = 0;
+    for (int p = 0; p < B; ++p) {
+        omt_ctx *c = h->ctx[p];
+        BatchPair &bp = h->pairs[p];
+        std::memset(&bp, 0, sizeof(bp));
+        const int ncolw = (c->r.n + WAVE - 1) / WAVE;
+        bp.type = batch_type(c->r.k, c->r.gk, c->r.lb);
+        bp.l = c->r.l;
+        bp.ncolw = ncolw;
+        bp.tile0 = t0;
+        bp.ntiles = L.ntiles[p];
+        bp.mcolw = ncolw;
+        bp.mtile0 = m0;
+        bp.mtiles = L.mtiles[p];
+        bp.mu = c->r.mu;
+        bp.nu = c->r.nu;
+        bp.tau = c->r.tau;
+        bp.R0 = c->r.tau * c->fnorm2;
+        for (int q = 0; q < L.ntiles[p]; ++q) tp.push_back(p);
+        for (int q = 0; q < L.mtiles[p]; ++q) mtp.push_back(p);
+        t0 += L.ntiles[p];
+        m0 += L.mtiles[p];
+    }
+    h->st.resize(B);
+    hipError_t e = hipMemcpyAsync(h->d_tile_pair, tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_mtile_pair, mtp.data(), sizeof(int) * mtp.size(), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+    int bpc = 0, cus = 0, dev = 0;
+    if (e == hipSuccess) e = batch_blocks_per_cu(comp, &bpc);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        destroy_batch(h);
+        return fail(OMT_EDEVICE, "batch set-up: %s", hipGetErrorString(e));
+    }
+    if (bpc < 1) {
+        destroy_batch(h);
+        return fail(OMT_EDEVICE, "batched kernel does not fit on a compute unit");
+    }
+    h->nblocks = bpc * cus;  // every workgroup resident at once
+    // remember the rows per strip in the per-problem arguments
+    for (int p = 0; p < B; ++p) h->ctx[p]->r.rows = L.rows[p];
+    *out = h;
+    return OMT_OK;
 }
-omt_status omt_batch_get_state(omt_batch_handle, int32_t, void *, void *, void *)
+
+omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, int32_t check_every, omt_info *infos)
 {
-    return fail(OMT_EUNSUPPORTED, "batched mode not built yet");
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    if (max_iters < 0) return fail(OMT_EINVAL, "max_iters < 0");
+    const int K = check_every > 0 ? check_every : 64;
+    if (max_iters == 0) {
+        for (int p = 0; p < h->B && infos; ++p) std::memset(&infos[p], 0, sizeof(omt_info));
+        return OMT_OK;
+    }
+    // step arguments for every (parity, w buffer, check) combination, from
+    // each problem's current buffers
+    for (int p = 0; p < h->B; ++p) {
+        omt_ctx *c = h->ctx[p];
+        BatchPair &bp = h->pairs[p];
+        const int ncolw = bp.ncolw, rows = c->r.rows, nroww = (c->r.m + rows - 1) / rows;
+        for (int var = 0; var < 8; ++var) {
+            const int par = var / 4, wv = (var / 2) % 2, chk = var % 2;
+            const int ci = (c->cur + par) & 1, wi = (c->wcur + wv) & 1;
+            fill_args(bp.v[var], c, ci, 1 - ci, wi, chk ? 1 - wi : wi, rows, ncolw, nroww, 0);
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_pairs, h->pairs.data(), sizeof(BatchPair) * h->B, hipMemcpyHostToDevice, h->cap));
+    BatchArgs ba;
+    ba.pairs = h->d_pairs;
+    ba.state = h->d_state;
+    ba.tile_pair = h->d_tile_pair;
+    ba.mtile_pair = h->d_mtile_pair;
+    ba.partials = h->d_partials;
+    ba.bar = h->d_bar;
+    ba.B = h->B;
+    ba.total_tiles = h->total_tiles;
+    ba.total_mtiles = h->total_mtiles;
+    ba.check_every = K;
+    ba.max_iters = max_iters;
+    ba.tol = tol;
+    // the whole solve is one graph: clear the barrier and states, then the
+    // persistent kernel
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_zero(h->d_state, sizeof(BatchPairState) * h->B, h->cap);
+    if (e == hipSuccess) e = launch_zero(h->d_bar, 256, h->cap);
+    if (e == hipSuccess) e = launch_batch(ba, h->comp, h->nblocks, h->cap);
+    hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(OMT_EDEVICE, "capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiateWithFlags(&exec, graph, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, h->cap);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->cap);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(OMT_EDEVICE, "batched solve: %s", hipGetErrorString(e));
+    unsigned bar[4];
+    HIP_TRY(hipMemcpy(bar, h->d_bar, sizeof(bar), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(h->st.data(), h->d_state, sizeof(BatchPairState) * h->B, hipMemcpyDeviceToHost));
+    if (bar[2] != 0u) return fail(OMT_EDEVICE, "batched solve: a grid barrier timed out (workgroups not co-resident)");
+    bool all = true, bad = false;
+    for (int p = 0; p < h->B; ++p) {
+        omt_ctx *c = h->ctx[p];
+        const BatchPairState &st = h->st[p];
+        omt_info inf;
+        std::memset(&inf, 0, sizeof(inf));
+        fill_info(c, st.met, &inf);
+        inf.iters = st.iters;
+        inf.checks = st.checks;
+        inf.converged = st.converged;
+        c->cur = (c->cur + (st.cur == 1 ? 1 : 0) + 0) & 1;
+        c->wcur = (c->wcur + (st.wcur == 1 ? 1 : 0)) & 1;
+        c->iters_done += st.iters;
+        c->last = inf;
+        c->have_last = true;
+        if (infos) infos[p] = inf;
+        if (!inf.converged) all = false;
+        if (!std::isfinite(inf.R)) bad = true;
+    }
+    if (bad) return fail(OMT_EDIVERGED, "a problem of the batch has a non-finite residual");
+    if (tol > 0.0 && !all) return fail(OMT_ENOTCONV, "some problems did not reach tol %.3g", tol);
+    return OMT_OK;
 }
-omt_status omt_batch_destroy(omt_batch_handle) { return OMT_OK; }
+
+omt_status omt_batch_distance(omt_batch_handle h, double *V)
+{
+    if (!h || !V) return fail(OMT_EINVAL, "handle or V is NULL");
+    for (int p = 0; p < h->B; ++p) {
+        omt_status s = omt_distance(h->ctx[p], &V[p], nullptr);
+        if (s != OMT_OK) return s;
+    }
+    return OMT_OK;
+}
+
+omt_status omt_batch_grad(omt_batch_handle h, void *const *d0, void *const *d1)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    for (int p = 0; p < h->B; ++p) {
+        omt_status s = omt_grad(h->ctx[p], d0 ? d0[p] : nullptr, d1 ? d1[p] : nullptr);
+        if (s != OMT_OK) return s;
+    }
+    return OMT_OK;
+}
+
+omt_status omt_batch_get_state(omt_batch_handle h, int32_t b, void *phi, void *u, void *w)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    if (b < 0 || b >= h->B) return fail(OMT_EINVAL, "problem index %d out of range", b);
+    return omt_get_state(h->ctx[b], phi, u, w);
+}
+
+omt_status omt_batch_destroy(omt_batch_handle h)
+{
+    if (h) destroy_batch(h);
+    return OMT_OK;
+}
 
 const char *omt_strerror(omt_status s)
 {

@@ -12,6 +12,7 @@ constexpr int KMAX = 8;    // channels
 constexpr int LMAX = 28;   // edges (complete graph on 8 nodes)
 constexpr int WAVE = 64;
 constexpr int STEP_WAVES_PER_WG = 4;
+constexpr int NMET = 8;  // su, sw, sp, cross, primal, dual, mass, sum_phi
 
 // Channel graphs the step kernel is compiled for.  The path (edges (c, c+1))
 // and the complete graph (all a < b in lexicographic order) get their
@@ -49,6 +50,7 @@ struct StepArgs {
     R mu, mu_h;            // mu, mu / h
     R nu, anu;             // nu, alpha nu
     R tau, inv_h;          // tau, 1 / h
+    double alpha;          // weight of the transfer term (objective)
     R ic[LMAX];            // 1 / c_e
     R gm[KMAX * LMAX];     // dense graphs: M = D diag(1/c), row c, column e at gm[c * LMAX + e]
 };
@@ -63,9 +65,49 @@ struct StepLaunch {
     hipStream_t stream;
 };
 
-// Defined once per channel count in step_k<K>.hip.
+// Defined once per channel count in step.hip (compiled per channel count).
 hipError_t launch_step(const StepLaunch &L);
 bool step_supported(int dtype, int k, int gk, int lb, int T, bool comp);
+// Per-tile metrics of the step args' (in -> out) buffers into partials
+// [ntiles][NMET]; tiles are 64 columns x 16 rows.
+hipError_t launch_tile_metrics(const StepLaunch &L, int ncolw, int ntiles, double *partials);
+// out[q] = sum of the ntiles rows of partials (one wave, fixed order).
+hipError_t launch_reduce_tiles(const double *partials, int ntiles, double *out, hipStream_t s);
+
+// ---------------------------------------------------------------- batched
+
+// One problem of a batch.  v[par * 4 + wcur * 2 + check] are its step
+// arguments for the iteration parity par (potential / flux buffers), the
+// current w buffer and whether the iteration is a check (w out of place).
+struct BatchPair {
+    StepArgs<float> v[8];
+    int type, l;
+    int ncolw, tile0, ntiles;   // step strips: across, first in the list, count
+    int mcolw, mtile0, mtiles;  // metric tiles likewise
+    double mu, nu, tau, R0;
+};
+
+struct BatchPairState {
+    int done, converged, cur, wcur;
+    int64_t iters;
+    int checks, pad;
+    double met[NMET];
+};
+
+struct BatchArgs {
+    const BatchPair *pairs;
+    BatchPairState *state;
+    const int *tile_pair, *mtile_pair;
+    double *partials;
+    unsigned *bar;  // [0] arrivals, [1] generation, [2] abort, [3] problems stopped
+    int B, total_tiles, total_mtiles, check_every;
+    int64_t max_iters;
+    double tol;
+};
+
+int batch_type(int k, int gk, int lb);  // -1 if not compiled into the batched kernel
+hipError_t batch_blocks_per_cu(bool comp, int *blocks);
+hipError_t launch_batch(const BatchArgs &a, bool comp, int nblocks, hipStream_t s);
 
 // ---------------------------------------------------------------- auxiliary
 
@@ -88,22 +130,6 @@ struct MakeFArgs {
     void *f;
 };
 hipError_t launch_make_f(const MakeFArgs &a, hipStream_t s);
-
-// Metrics of the step (old -> new); old == new gives objectives of one iterate.
-struct MetricArgs {
-    const void *phi0, *phi1, *u0, *u1, *w0, *w1, *f;
-    const float *plo0, *plo1;
-    int dtype;
-    int m, n, k, l, pitch;
-    int64_t plane;
-    int unorm, wnorm;
-    double inv_h, alpha;
-    double gm[KMAX * LMAX];
-    double *partials;   // [nblocks][NMET]
-    int nblocks;
-};
-constexpr int NMET = 8;  // su, sw, sp, cross, primal, dual, mass, sum_phi
-hipError_t launch_metrics(const MetricArgs &a, hipStream_t s);
 
 // Sum nblocks rows of width `width` in a fixed order into out[width].
 hipError_t launch_reduce_rows(const double *partials, int nblocks, int width, double *out, hipStream_t s);

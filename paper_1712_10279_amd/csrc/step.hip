@@ -26,7 +26,7 @@
 //
 // Compiled once per channel count (OMT_K) to keep build units small.
 
-#include "omt_kernels.h"
+#include "metrics_device.h"
 
 #ifndef OMT_K
 #error "compile with -DOMT_K=<channels>"
@@ -35,490 +35,32 @@
 namespace omt {
 namespace {
 
-// ------------------------------------------------------------ lane moves
-
-__device__ __forceinline__ float lane_next(float v) { return __shfl_down(v, 1u, WAVE); }
-__device__ __forceinline__ float lane_prev(float v) { return __shfl_up(v, 1u, WAVE); }
-__device__ __forceinline__ double lane_next(double v) { return __shfl_down(v, 1u, WAVE); }
-__device__ __forceinline__ double lane_prev(double v) { return __shfl_up(v, 1u, WAVE); }
-
-// value of lane L (a wave-uniform result)
-__device__ __forceinline__ float lane_get(float v, int L)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
-}
-__device__ __forceinline__ double lane_get(double v, int L)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), L);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), L);
-    return __hiloint2double(hi, lo);
-}
-
-// ------------------------------------------------------------ shrinks (App. B)
-
-template <typename R>
-__device__ __forceinline__ R shrink_scale(R r, R t)
-{
-    // (1 - t/r) for r >= t, else 0: the factor applied to the block.
-    return (r >= t && r > R(0)) ? R(1) - t / r : R(0);
-}
-
-template <typename R, int K>
-__device__ __forceinline__ void shrink_u(int unorm, R (&bx)[K], R (&by)[K], R t)
-{
-    if (unorm == 0) {  // sum over channels of ||(u_x, u_y)||_2
-#pragma unroll
-        for (int c = 0; c < K; ++c) {
-            const R s = shrink_scale(sqrt(bx[c] * bx[c] + by[c] * by[c]), t);
-            bx[c] = bx[c] * s;
-            by[c] = by[c] * s;
-        }
-    } else if (unorm == 1) {  // element-wise
-#pragma unroll
-        for (int c = 0; c < K; ++c) {
-            bx[c] = bx[c] * shrink_scale(fabs(bx[c]), t);
-            by[c] = by[c] * shrink_scale(fabs(by[c]), t);
-        }
-    } else {  // one block of all 2k components
-        R r2 = R(0);
-#pragma unroll
-        for (int c = 0; c < K; ++c) r2 = r2 + bx[c] * bx[c];
-#pragma unroll
-        for (int c = 0; c < K; ++c) r2 = r2 + by[c] * by[c];
-        const R s = shrink_scale(sqrt(r2), t);
-#pragma unroll
-        for (int c = 0; c < K; ++c) {
-            bx[c] = bx[c] * s;
-            by[c] = by[c] * s;
-        }
-    }
-}
-
-template <typename R, int L>
-__device__ __forceinline__ void shrink_w(int wnorm, R (&w)[L], R t)
-{
-    if (wnorm == 0) {
-#pragma unroll
-        for (int e = 0; e < L; ++e) w[e] = w[e] * shrink_scale(fabs(w[e]), t);
-    } else {
-        R r2 = R(0);
-#pragma unroll
-        for (int e = 0; e < L; ++e) r2 = r2 + w[e] * w[e];
-        const R s = shrink_scale(sqrt(r2), t);
-#pragma unroll
-        for (int e = 0; e < L; ++e) w[e] = w[e] * s;
-    }
-}
-
-// ------------------------------------------------------------ channel graph
-
-// Endpoints (a_e, b_e), a_e < b_e, of edge e of the compiled graph kinds.
-constexpr int complete_row_start(int K, int a) { return a * (K - 1) - a * (a - 1) / 2; }
-template <int GK, int K>
-constexpr int edge_a(int e)
-{
-    if (GK == G_PATH) return e;
-    int a = 0;
-    while (a + 1 < K && complete_row_start(K, a + 1) <= e) ++a;
-    return a;
-}
-template <int GK, int K>
-constexpr int edge_b(int e)
-{
-    if (GK == G_PATH) return e + 1;
-    const int a = edge_a<GK, K>(e);
-    return a + 1 + (e - complete_row_start(K, a));
-}
-
-// ------------------------------------------------------------ one stage
-
-// Columns just outside an aligned strip, lane c holding channel c: the
-// potential one column to the right (row r) and, one column to the left,
-// the potential on rows r and r+1 and the flux on row r.
-template <typename R>
-struct Edges {
-    R RA, RAl, LA, LAl, LB, LBl, Lux, Luy;
-    bool hasL;
-};
-
-// Iteration of one pixel row r for this lane's column.  pA/pB: potential
-// on rows r and r+1 (hi and, if COMP, lo parts); ux, uy, w: state on row r;
-// carry: 2u'_x - u_x of row r-1 on entry, of row r on exit.  Outputs go to
-// pO/pOl/uxO/uyO/wO and, if st is set, straight to memory at offset o.  In
-// the aligned mode (ALN) lane 63 takes its right potential and lane 0 its
-// left flux from E instead of the neighbouring lane; the left flux is
-// recomputed with the same expressions as every other pixel's.
-template <typename R, int K, int GK, int L, int LA, bool COMP, bool ALN>
-__device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_ok, bool last_row, bool last_col,
-                                      const R (&pA)[K], const R (&pAl)[K], const R (&pB)[K], const R (&pBl)[K],
-                                      const R (&ux)[K], const R (&uy)[K], const R (&w)[LA], const R (&f)[K],
-                                      const Edges<R> &E, bool st, int64_t o, R (&carry)[K], R (&pO)[K],
-                                      R (&pOl)[K], R (&uxO)[K], R (&uyO)[K], R (&wO)[LA])
-{
-    const int64_t P = a.plane;
-
-    // w-update: shrink_w(w + nu grad_G phi, alpha nu); (grad_G phi)_e =
-    // (phi_a - phi_b) / c_e (Sec. 3.1), or M^T phi for a dense graph
-    R wb[LA];
-    if constexpr (L > 0) {
-        R wt[LA];
-#pragma unroll
-        for (int e = 0; e < LA; ++e) {
-            R s = R(0);
-            if constexpr (GK == G_DENSE) {
-#pragma unroll
-                for (int c = 0; c < K; ++c) {
-                    s = s + a.gm[c * LMAX + e] * pA[c];
-                    if (COMP) s = s + a.gm[c * LMAX + e] * pAl[c];
-                }
-                wt[e] = (e < a.l) ? w[e] + a.nu * s : R(0);
-            } else {
-                const int ea = edge_a<GK, K>(e), eb = edge_b<GK, K>(e);
-                s = pA[ea] - pA[eb];
-                if (COMP) s = s + (pAl[ea] - pAl[eb]);
-                wt[e] = w[e] + a.nu * (s * a.ic[e]);
-            }
-        }
-        shrink_w<R, LA>(a.wnorm, wt, a.anu);
-#pragma unroll
-        for (int e = 0; e < LA; ++e) {
-            if (!lane_ok) wt[e] = R(0);
-            wO[e] = wt[e];
-            wb[e] = R(2) * wt[e] - w[e];
-            if (st && e < a.l) a.w_out[e * P + o] = wt[e];
-        }
-    }
-
-    // u~ = u + mu grad_x phi for this lane's pixel and, in the aligned mode,
-    // for the pixel left of the strip (wave-uniform)
-    auto utilde = [&](int c, R &tx, R &ty) {
-        R pr = lane_next(pA[c]);
-        R prl = COMP ? lane_next(pAl[c]) : R(0);
-        if (ALN && lane == WAVE - 1) {
-            pr = lane_get(E.RA, c);
-            prl = COMP ? lane_get(E.RAl, c) : R(0);
-        }
-        R gx = pB[c] - pA[c];
-        R gy = pr - pA[c];
-        if (COMP) {
-            gx = gx + (pBl[c] - pAl[c]);
-            gy = gy + (prl - pAl[c]);
-        }
-        tx = last_row ? R(0) : ux[c] + a.mu_h * gx;
-        ty = last_col ? R(0) : uy[c] + a.mu_h * gy;
-    };
-    auto utilde_left = [&](int c, R &tx, R &ty) {
-        const R hA = lane_get(E.LA, c), hB = lane_get(E.LB, c), hR = lane_get(pA[c], 0);
-        R gx = hB - hA;
-        R gy = hR - hA;
-        if (COMP) {
-            const R hAl = lane_get(E.LAl, c), hBl = lane_get(E.LBl, c), hRl = lane_get(pAl[c], 0);
-            gx = gx + (hBl - hAl);
-            gy = gy + (hRl - hAl);
-        }
-        tx = last_row ? R(0) : lane_get(E.Lux, c) + a.mu_h * gx;
-        ty = lane_get(E.Luy, c) + a.mu_h * gy;  // the left column is never the last one
-    };
-    // ||u||_2 over all 2k components needs the norm of the whole block first
-    R s_all = R(0), s_left = R(0);
-    if (a.unorm == 2) {
-        R r2 = R(0), r2l = R(0), tx, ty;
-#pragma unroll
-        for (int c = 0; c < K; ++c) {
-            utilde(c, tx, ty);
-            r2 = r2 + tx * tx;
-            if (ALN) {
-                utilde_left(c, tx, ty);
-                r2l = r2l + tx * tx;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < K; ++c) {
-            utilde(c, tx, ty);
-            r2 = r2 + ty * ty;
-            if (ALN) {
-                utilde_left(c, tx, ty);
-                r2l = r2l + ty * ty;
-            }
-        }
-        s_all = shrink_scale<R>(sqrt(r2), a.mu);
-        s_left = shrink_scale<R>(sqrt(r2l), a.mu);
-    }
-    auto shrink_pair = [&](R tx, R ty, R sblock, R &bx, R &by) {
-        if (a.unorm == 0) {  // sum over channels of ||(u_x, u_y)||_2 (App. B shrink_2 per channel)
-            const R s = shrink_scale<R>(sqrt(tx * tx + ty * ty), a.mu);
-            bx = tx * s;
-            by = ty * s;
-        } else if (a.unorm == 1) {  // element-wise shrink_1
-            bx = tx * shrink_scale<R>(fabs(tx), a.mu);
-            by = ty * shrink_scale<R>(fabs(ty), a.mu);
-        } else {
-            bx = tx * sblock;
-            by = ty * sblock;
-        }
-    };
-
-    // per channel: u-update, extrapolation, divergences, phi-update
-#pragma unroll
-    for (int c = 0; c < K; ++c) {
-        R tx, ty, bx, by;
-        utilde(c, tx, ty);
-        shrink_pair(tx, ty, s_all, bx, by);
-        if (!lane_ok) bx = by = R(0);
-        const R ubx = R(2) * bx - ux[c];
-        const R uby = R(2) * by - uy[c];
-        R ubl = lane_prev(uby);
-        if (ALN) {
-            R ex, ey, ebx, eby;
-            utilde_left(c, ex, ey);
-            shrink_pair(ex, ey, s_left, ebx, eby);
-            const R el = E.hasL ? R(2) * eby - lane_get(E.Luy, c) : R(0);
-            if (lane == 0) ubl = el;
-        }
-        const R dx = (((ubx - carry[c]) + uby) - ubl) * a.inv_h;
-        // div_G(w) = -D diag(1/c) w: dg is D diag(1/c) w, accumulated in edge order
-        R dg = R(0);
-        if constexpr (L > 0) {
-#pragma unroll
-            for (int e = 0; e < LA; ++e) {
-                if constexpr (GK == G_DENSE) {
-                    dg = dg + a.gm[c * LMAX + e] * wb[e];
-                } else {
-                    if (edge_a<GK, K>(e) == c) dg = dg + a.ic[e] * wb[e];
-                    if (edge_b<GK, K>(e) == c) dg = dg - a.ic[e] * wb[e];
-                }
-            }
-        }
-        const R inc = a.tau * ((dx - dg) + f[c]);
-        R po, pol = R(0);
-        if (COMP) {
-            // error-free sum of (hi, lo) and the increment (TwoSum)
-            const R t = pAl[c] + inc;
-            const R s = pA[c] + t;
-            const R bb = s - pA[c];
-            const R err = (pA[c] - (s - bb)) + (t - bb);
-            po = lane_ok ? s : R(0);
-            pol = lane_ok ? err : R(0);
-        } else {
-            po = lane_ok ? pA[c] + inc : R(0);
-        }
-        carry[c] = ubx;
-        pO[c] = po;
-        pOl[c] = pol;
-        uxO[c] = bx;
-        uyO[c] = by;
-        if (st) {
-            a.phi_out[c * P + o] = po;
-            if (COMP) a.plo_out[c * P + o] = float(pol);
-            a.u_out[c * P + o] = bx;
-            a.u_out[(K + c) * P + o] = by;
-        }
-    }
-}
-
-__device__ __forceinline__ int xcd_remap(int b, int nwg)
-{
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
-    // contiguous range of tiles (a band of rows) so that halo rows and
-    // columns shared by neighbouring waves hit in that XCD's L2.
-    constexpr int NX = 8;
-    const int x = b % NX, idx = b / NX;
-    const int q = nwg / NX, r = nwg % NX;
-    return (x < r) ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
-}
+using namespace dev;
 
 template <typename R, int K, int GK, int L, int T, bool COMP>
 __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step_kernel(const StepArgs<R> a)
 {
-    constexpr int LA = L > 0 ? L : 1;
-    constexpr bool ALN = (T == 1);  // aligned 64-column strips
     const int lane = threadIdx.x & (WAVE - 1);
     const int g = xcd_remap(blockIdx.x, a.nwg);
     const int wc = g % a.ncolw;
     const int wr = (g / a.ncolw) * STEP_WAVES_PER_WG + (threadIdx.x / WAVE);
     if (wr >= a.nroww) return;  // whole wave leaves; no barriers follow
+    process_strip<R, K, GK, L, T, COMP>(a, wc, wr, lane);
+}
 
-    const int j = ALN ? wc * WAVE + lane : wc * (WAVE - 2 * T) - T + lane;
-    const bool jin = (j >= 0) && (j < a.n);
-    const bool jout = ALN ? jin : (jin && lane >= T && lane < WAVE - T);
-    const bool last_col = (j == a.n - 1);
-    const int jc = jin ? j : 0;
-    const int i0 = wr * a.rows;
-    const int i1 = min(i0 + a.rows, a.m);
-    const int rs = max(i0 - T, 0);
-    const int re = min(i1 + T - 1, a.m);
-    const int64_t P = a.plane;
-    const int pitch = a.pitch;
-
-    const R *__restrict__ phi = a.phi_in + jc;
-    const float *__restrict__ plo = COMP ? a.plo_in + jc : nullptr;
-    const R *__restrict__ uin = a.u_in + jc;
-    const R *__restrict__ win = a.w_in + jc;
-    const R *__restrict__ fin = a.f + jc;
-
-    // aligned mode: columns just outside the strip, lane c holding channel c
-    const int jL = wc * WAVE - 1, jR = wc * WAVE + WAVE;
-    const bool hasL = ALN && jL >= 0, hasR = ALN && jR < a.n;
-    const bool hl = lane < K;
-    const int hc = hl ? lane : 0;
-    auto ld_edge = [&](int col, int r, const R *base, int plane0) -> R {
-        return base[(plane0 + hc) * P + (int64_t)r * pitch + col];
-    };
-    auto ld_edge_lo = [&](int col, int r) -> R {
-        return R(a.plo_in[hc * P + (int64_t)r * pitch + col]);
-    };
-    // next-row values (prefetched) of the edge columns
-    R nRA = R(0), nRAl = R(0);                    // phi(r, jR)
-    R nLA = R(0), nLAl = R(0), nLB = R(0), nLBl = R(0);  // phi(r, jL), phi(r+1, jL)
-    R nLux = R(0), nLuy = R(0);                   // u(r, jL)
-
-    // stage-0 inputs of the next row, loaded one step ahead
-    R nA[K], nAl[K], nB[K], nBl[K], nux[K], nuy[K], nw[LA], nf[K];
-    auto load_phi = [&](int r, R (&hi)[K], R (&lo)[K]) {
+template <typename R, int K, int GK, int L, bool COMP>
+__global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void tile_metrics_kernel(const StepArgs<R> a, int ncolw,
+                                                                                int ntiles, double *partials)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int t = blockIdx.x * STEP_WAVES_PER_WG + threadIdx.x / WAVE;
+    if (t >= ntiles) return;
+    double v[NMET];
+    tile_metrics<R, K, GK, L, COMP>(a, t % ncolw, t / ncolw, lane, v);
 #pragma unroll
-        for (int c = 0; c < K; ++c) {
-            hi[c] = (jin && r < a.m) ? phi[c * P + (int64_t)r * pitch] : R(0);
-            lo[c] = (COMP && jin && r < a.m) ? R(plo[c * P + (int64_t)r * pitch]) : R(0);
-        }
-    };
-    // a single-iteration launch needs no w or f on its top halo row
-    auto load_rest = [&](int r) {
-        const int64_t o = (int64_t)r * pitch;
-        const bool full = !ALN || r >= i0;
-#pragma unroll
-        for (int c = 0; c < K; ++c) {
-            nux[c] = jin ? uin[c * P + o] : R(0);
-            nuy[c] = jin ? uin[(K + c) * P + o] : R(0);
-            nf[c] = (jin && full) ? fin[c * P + o] : R(0);
-        }
-#pragma unroll
-        for (int e = 0; e < LA; ++e) nw[e] = (L > 0 && jin && full && e < a.l) ? win[e * P + o] : R(0);
-    };
-    auto load_edges_first = [&](int r) {
-        if (hasR && hl) {
-            nRA = ld_edge(jR, r, a.phi_in, 0);
-            if (COMP) nRAl = ld_edge_lo(jR, r);
-        }
-        if (hasL && hl) {
-            nLA = ld_edge(jL, r, a.phi_in, 0);
-            if (COMP) nLAl = ld_edge_lo(jL, r);
-            if (r + 1 < a.m) {
-                nLB = ld_edge(jL, r + 1, a.phi_in, 0);
-                if (COMP) nLBl = ld_edge_lo(jL, r + 1);
-            }
-            nLux = ld_edge(jL, r, a.u_in, 0);
-            nLuy = ld_edge(jL, r, a.u_in, K);
-        }
-    };
-    load_phi(rs, nA, nAl);
-    load_phi(rs + 1, nB, nBl);
-    load_rest(rs);
-    if (ALN) load_edges_first(rs);
-
-    // pipeline registers: outputs of stage t on the previous (P) and the
-    // current (N) step, and each stage's carry and source term
-    R phP[T][K], plP[T][K], phN[T][K], plN[T][K];
-    R uxP[T][K], uyP[T][K], wP[T][LA];
-    R uxN[T][K], uyN[T][K], wN[T][LA];
-    R carry[T][K], fq[T][K];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-#pragma unroll
-        for (int c = 0; c < K; ++c) {
-            phP[t][c] = plP[t][c] = phN[t][c] = plN[t][c] = R(0);
-            uxP[t][c] = uyP[t][c] = uxN[t][c] = uyN[t][c] = R(0);
-            carry[t][c] = fq[t][c] = R(0);
-        }
-#pragma unroll
-        for (int e = 0; e < LA; ++e) wP[t][e] = wN[t][e] = R(0);
-    }
-
-    const int nsteps = (re - rs) + T - 1;
-    for (int s = 0; s < nsteps; ++s) {
-        const int r0 = rs + s;
-        // current stage-0 inputs
-        R cA[K], cAl[K], cB[K], cBl[K], cux[K], cuy[K], cw[LA];
-#pragma unroll
-        for (int c = 0; c < K; ++c) {
-            cA[c] = nA[c];
-            cAl[c] = nAl[c];
-            cB[c] = nB[c];
-            cBl[c] = nBl[c];
-            cux[c] = nux[c];
-            cuy[c] = nuy[c];
-        }
-#pragma unroll
-        for (int e = 0; e < LA; ++e) cw[e] = nw[e];
-#pragma unroll
-        for (int t = T - 1; t > 0; --t) {
-#pragma unroll
-            for (int c = 0; c < K; ++c) fq[t][c] = fq[t - 1][c];
-        }
-#pragma unroll
-        for (int c = 0; c < K; ++c) fq[0][c] = nf[c];
-        const R cRA = nRA, cRAl = nRAl, cLA = nLA, cLAl = nLAl, cLB = nLB, cLBl = nLBl, cLux = nLux, cLuy = nLuy;
-
-        // prefetch the next row while this one is computed
-        if (r0 + 1 < re) {
-#pragma unroll
-            for (int c = 0; c < K; ++c) {
-                nA[c] = cB[c];
-                nAl[c] = cBl[c];
-            }
-            load_phi(r0 + 2, nB, nBl);
-            load_rest(r0 + 1);
-            if (ALN) {
-                if (hasR && hl) {
-                    nRA = ld_edge(jR, r0 + 1, a.phi_in, 0);
-                    if (COMP) nRAl = ld_edge_lo(jR, r0 + 1);
-                }
-                if (hasL && hl) {
-                    nLA = cLB;
-                    nLAl = cLBl;
-                    if (r0 + 2 < a.m) {
-                        nLB = ld_edge(jL, r0 + 2, a.phi_in, 0);
-                        if (COMP) nLBl = ld_edge_lo(jL, r0 + 2);
-                    }
-                    nLux = ld_edge(jL, r0 + 1, a.u_in, 0);
-                    nLuy = ld_edge(jL, r0 + 1, a.u_in, K);
-                }
-            }
-        }
-
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const int r = r0 - t;
-            if (r >= rs && r < re) {
-                const bool last_row = (r == a.m - 1);
-                const bool st = (t == T - 1) && jout && r >= i0 && r < i1;
-                const int64_t o = (int64_t)r * pitch + j;
-                if (t == 0) {
-                    Edges<R> E{cRA, cRAl, cLA, cLAl, cLB, cLBl, cLux, cLuy, hasL};
-                    stage<R, K, GK, L, LA, COMP, ALN>(a, lane, jin, last_row, last_col, cA, cAl, cB, cBl, cux, cuy,
-                                                      cw, fq[0], E, st, o, carry[0], phN[0], plN[0], uxN[0], uyN[0],
-                                                      wN[0]);
-                } else {
-                    Edges<R> E{R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), false};
-                    stage<R, K, GK, L, LA, COMP, false>(a, lane, jin, last_row, last_col, phP[t - 1], plP[t - 1],
-                                                        phN[t - 1], plN[t - 1], uxP[t - 1], uyP[t - 1], wP[t - 1],
-                                                        fq[t], E, st, o, carry[t], phN[t], plN[t], uxN[t], uyN[t],
-                                                        wN[t]);
-                }
-            }
-        }
-        // rotate: this step's outputs become the next step's inputs
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-#pragma unroll
-            for (int c = 0; c < K; ++c) {
-                phP[t][c] = phN[t][c];
-                plP[t][c] = plN[t][c];
-                uxP[t][c] = uxN[t][c];
-                uyP[t][c] = uyN[t][c];
-            }
-#pragma unroll
-            for (int e = 0; e < LA; ++e) wP[t][e] = wN[t][e];
-        }
+    for (int q = 0; q < NMET; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) partials[(int64_t)t * NMET + q] = s;
     }
 }
 
@@ -529,6 +71,24 @@ hipError_t launch_one(const StepLaunch &Lc)
     hipLaunchKernelGGL((pdhg_step_kernel<R, OMT_K, GK, L, T, COMP>), dim3(a.nwg), dim3(WAVE * STEP_WAVES_PER_WG), 0,
                        Lc.stream, a);
     return hipGetLastError();
+}
+
+template <typename R, int GK, int L, bool COMP>
+hipError_t launch_met(const StepLaunch &Lc, int ncolw, int ntiles, double *partials)
+{
+    const StepArgs<R> &a = *static_cast<const StepArgs<R> *>(Lc.args);
+    const int nb = (ntiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG;
+    hipLaunchKernelGGL((tile_metrics_kernel<R, OMT_K, GK, L, COMP>), dim3(nb), dim3(WAVE * STEP_WAVES_PER_WG), 0,
+                       Lc.stream, a, ncolw, ntiles, partials);
+    return hipGetLastError();
+}
+
+template <int GK, int L>
+hipError_t dispatch_met(const StepLaunch &Lc, int ncolw, int ntiles, double *partials)
+{
+    if (Lc.dtype == 1) return launch_met<double, GK, L, false>(Lc, ncolw, ntiles, partials);
+    return Lc.comp ? launch_met<float, GK, L, true>(Lc, ncolw, ntiles, partials)
+                   : launch_met<float, GK, L, false>(Lc, ncolw, ntiles, partials);
 }
 
 // Blocking depths compiled for this channel count (register budget); dense
@@ -576,6 +136,20 @@ hipError_t OMT_CAT(launch_step_k, OMT_K)(const StepLaunch &Lc)
     if (Lc.gk == G_COMPLETE && Lc.lb == L_FULL) return dispatch_T<G_COMPLETE, L_FULL>(Lc);
     if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return dispatch_T<G_DENSE, L_TREE>(Lc);
     if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return dispatch_T<G_DENSE, L_FULL>(Lc);
+#endif
+    return hipErrorInvalidValue;
+}
+
+hipError_t OMT_CAT(launch_metrics_k, OMT_K)(const StepLaunch &Lc, int ncolw, int ntiles, double *partials)
+{
+    if (Lc.gk == G_NONE && Lc.lb == 0) return dispatch_met<G_NONE, 0>(Lc, ncolw, ntiles, partials);
+#if OMT_K >= 2
+    if (Lc.gk == G_PATH && Lc.lb == L_TREE) return dispatch_met<G_PATH, L_TREE>(Lc, ncolw, ntiles, partials);
+#endif
+#if OMT_K >= 3
+    if (Lc.gk == G_COMPLETE && Lc.lb == L_FULL) return dispatch_met<G_COMPLETE, L_FULL>(Lc, ncolw, ntiles, partials);
+    if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return dispatch_met<G_DENSE, L_TREE>(Lc, ncolw, ntiles, partials);
+    if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return dispatch_met<G_DENSE, L_FULL>(Lc, ncolw, ntiles, partials);
 #endif
     return hipErrorInvalidValue;
 }

@@ -302,3 +302,78 @@ def omt_loss(rho0, rho1, edges=None, max_iters=100000, tol=1e-6, check_every=64,
         return torch.stack([_OMT_FN.apply(rho0[b], rho1[b], edges, max_iters, tol, check_every, kw)
                             for b in range(rho0.shape[0])])
     return _OMT_FN.apply(rho0, rho1, edges, max_iters, tol, check_every, kw)
+
+
+class BatchSolver:
+    """Many problems solved together by the persistent batched kernel
+    (omt_batch_create ... omt_batch_destroy).  ``problems`` is a list of
+    dicts with keys rho0, rho1 (GPU tensors, float32), edges and any Config
+    field (alpha, tau, compensated, ...)."""
+
+    def __init__(self, problems):
+        torch = _torch()
+        self.B = len(problems)
+        ps = (Params * self.B)()
+        self._keep = []
+        self.shapes = []
+        r0 = (C.c_void_p * self.B)()
+        r1 = (C.c_void_p * self.B)()
+        dev = None
+        for b, pr in enumerate(problems):
+            a0, a1 = pr["rho0"].contiguous(), pr["rho1"].contiguous()
+            if a0.dtype != torch.float32 or not a0.is_cuda:
+                raise ValueError("batched problems must be float32 GPU tensors")
+            dev = a0.device
+            m, n, k = (int(x) for x in a0.shape)
+            edges = np.zeros((0, 2), np.int32) if pr.get("edges") is None else pr["edges"]
+            kw = {key: v for key, v in pr.items() if key not in ("rho0", "rho1", "edges")}
+            p, keep = make_params(m, n, k, edges, Config(**kw), F32)
+            ps[b] = p
+            self._keep += [keep, a0, a1]
+            r0[b], r1[b] = a0.data_ptr(), a1.data_ptr()
+            self.shapes.append((m, n, k, int(np.asarray(edges).reshape(-1, 2).shape[0])))
+        nbytes = C.c_size_t()
+        _check(lib().omt_batch_workspace_bytes(self.B, ps, C.byref(nbytes)), "omt_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        self.device = dev
+        h = C.c_void_p()
+        _check(lib().omt_batch_create(self.B, ps, r0, r1, _ptr(self.workspace), nbytes.value, _stream_ptr(),
+                                      C.byref(h)), "omt_batch_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.omt_batch_destroy(h)
+            self._h = None
+
+    def solve(self, max_iters, tol=0.0, check_every=64, allow_notconv=True):
+        infos = (Info * self.B)()
+        allow = (ENOTCONV,) if allow_notconv else ()
+        _check(lib().omt_batch_solve(self._h, int(max_iters), float(tol), int(check_every), infos),
+               "omt_batch_solve", allow)
+        return [i.as_dict() for i in infos]
+
+    def distance(self):
+        V = (C.c_double * self.B)()
+        _check(lib().omt_batch_distance(self._h, V), "omt_batch_distance")
+        return list(V)
+
+    def grad(self):
+        torch = _torch()
+        d0 = [torch.empty(s[:3], dtype=torch.float32, device=self.device) for s in self.shapes]
+        d1 = [torch.empty_like(x) for x in d0]
+        p0 = (C.c_void_p * self.B)(*[x.data_ptr() for x in d0])
+        p1 = (C.c_void_p * self.B)(*[x.data_ptr() for x in d1])
+        _check(lib().omt_batch_grad(self._h, p0, p1), "omt_batch_grad")
+        return d0, d1
+
+    def get_state(self, b):
+        torch = _torch()
+        m, n, k, l = self.shapes[b]
+        phi = torch.empty((m, n, k), dtype=torch.float32, device=self.device)
+        u = torch.empty((m, n, k, 2), dtype=torch.float32, device=self.device)
+        w = torch.zeros((m, n, max(l, 1)), dtype=torch.float32, device=self.device)
+        _check(lib().omt_batch_get_state(self._h, int(b), _ptr(phi), _ptr(u), _ptr(w) if l else C.c_void_p(0)),
+               "omt_batch_get_state")
+        return {"phi": phi, "u": u, "w": w[:, :, :l]}

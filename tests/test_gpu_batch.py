@@ -1,0 +1,89 @@
+"""The persistent batched kernel against per-problem solves (and, through
+them, the oracle): every problem of a batch must end with bit-identical
+iterates, iteration counts and stopping decisions to its own solve."""
+import numpy as np
+import pytest
+
+from gpu_util import cuda, note, to_dev
+from paper_1712_10279_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # (m, n, k, edges)
+    (64, 64, 1, None),
+    (70, 130, 3, I.TRIANGLE),
+    (33, 65, 2, [(0, 1)]),
+    (128, 96, 3, I.path_edges(3)),
+    (2, 5, 3, I.TRIANGLE),
+    (150, 40, 1, None),
+]
+
+
+def _problems(torch, seed, comp=False, tau=None):
+    out = []
+    for q, (m, n, k, e) in enumerate(SHAPES):
+        r0, r1 = I.random_pair(seed + q, m, n, k)
+        out.append(dict(rho0=to_dev(torch, r0, torch.float32), rho1=to_dev(torch, r1, torch.float32), edges=e,
+                        alpha=0.5 + 0.3 * q, tau=tau or I.default_tau(m, n), compensated=comp))
+    return out
+
+
+def _plain(torch, pr, iters, tol):
+    from paper_1712_10279_amd import omt
+    kw = {key: v for key, v in pr.items() if key not in ("rho0", "rho1", "edges")}
+    s = omt.Solver(pr["rho0"], pr["rho1"], pr["edges"], **kw)
+    info = s.solve(iters, tol, 64)
+    return s, info
+
+
+@pytest.mark.parametrize("comp", [False, True])
+def test_batch_fixed_iterations_bit_identical(comp):
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    probs = _problems(torch, 40, comp)
+    note(f"case: batch of {len(probs)} fixed 300 iterations comp={comp}")
+    b = omt.BatchSolver(probs)
+    infos = b.solve(300, 0.0, 64)
+    Vb = b.distance()
+    for q, pr in enumerate(probs):
+        s, info = _plain(torch, pr, 300, 0.0)
+        assert infos[q]["iters"] == info["iters"] == 300
+        gs, bs = s.get_state(), b.get_state(q)
+        for key in ("phi", "u", "w"):
+            assert torch.equal(gs[key], bs[key]), (q, key)
+        assert infos[q]["residual"] == info["residual"]
+        assert Vb[q] == s.distance()[0]
+
+
+def test_batch_to_tolerance_same_decisions():
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    probs = _problems(torch, 50, True)
+    note("case: batch to tol 1e-3")
+    b = omt.BatchSolver(probs)
+    infos = b.solve(200000, 1e-3, 64)
+    for q, pr in enumerate(probs):
+        s, info = _plain(torch, pr, 200000, 1e-3)
+        note(f"  problem {q}: batch {infos[q]['iters']} it conv {infos[q]['converged']}, "
+             f"plain {info['iters']} it conv {info['converged']}")
+        assert infos[q]["iters"] == info["iters"]
+        assert infos[q]["converged"] == info["converged"] == 1
+        gs, bs = s.get_state(), b.get_state(q)
+        for key in ("phi", "u", "w"):
+            assert torch.equal(gs[key], bs[key]), (q, key)
+    # a second solve continues from where each problem stopped
+    infos2 = b.solve(128, 0.0, 64)
+    assert all(i["iters"] == 128 for i in infos2)
+    d0, d1 = b.grad()
+    for q in range(len(probs)):
+        assert torch.equal(d0[q], -d1[q])
+
+
+def test_batch_rejects_unsupported_problem():
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    r0, r1 = I.random_pair(60, 20, 20, 5)
+    with pytest.raises(omt.OMTError) as e:
+        omt.BatchSolver([dict(rho0=to_dev(torch, r0, torch.float32), rho1=to_dev(torch, r1, torch.float32),
+                              edges=I.path_edges(5))])
+    assert e.value.status == omt.EUNSUPPORTED
