@@ -38,6 +38,12 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations for the CPU baseline (0: auto)")
     ap.add_argument("--timing-launches", type=int, default=200)
+    ap.add_argument("--workload", default="large", choices=["large", "batched", "rgb", "loss"],
+                    help="large: 1024x1024 k=8 throughput (default); batched: 96 pairs to 1e-5, batched vs "
+                         "plain; rgb: 256x256 k=3 time to 1e-5; loss: 8 pairs of 512x512 forward+backward")
+    ap.add_argument("--pairs", type=int, default=96, help="batched workload: number of pairs")
+    ap.add_argument("--tol", type=float, default=0.0, help="time-to-tolerance workloads: tolerance (0: workload's)")
+    ap.add_argument("--cap", type=int, default=3_000_000, help="time-to-tolerance workloads: iteration cap")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device-to-device copies of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -93,10 +99,116 @@ def cpu_baseline(d, iters):
                       f"{r['wall_s']:.1f} s"}
 
 
+def _line(metric, value, unit, steps, warmup, ms, config, dtype="f32", **extra):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+         "ms_per_step": ms, "higher_is_better": unit.endswith("/s") or unit == "x", "scaling": "weak",
+         "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    d.update(extra)
+    return d
+
+
+def bench_batched(a):
+    """96 pairs (sides 64..512, k in {1, 3}) to a relative residual of 1e-5:
+    the persistent batched kernel against the per-pair solves, same tau, K,
+    tol and compensated FP32 potential (identical iteration counts)."""
+    import torch
+    from paper_1712_10279_amd import inputs as I
+    from paper_1712_10279_amd import omt
+    tol = a.tol or 1e-5
+    specs = I.batch_spec(a.pairs)
+    probs = []
+    for sp in specs:
+        d = I.batch_pair(sp)
+        probs.append(dict(rho0=torch.as_tensor(d["rho0"], dtype=torch.float32, device="cuda"),
+                          rho1=torch.as_tensor(d["rho1"], dtype=torch.float32, device="cuda"),
+                          edges=d["edges"], alpha=d["alpha"], tau=I.tuned_tau(sp["side"], sp["side"]),
+                          compensated=True))
+    # plain: one solve after another on one stream
+    solvers = [omt.Solver(p["rho0"], p["rho1"], p["edges"], alpha=p["alpha"], tau=p["tau"], compensated=True)
+               for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [s.solve(a.cap, tol, 64) for s in solvers]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    del solvers
+    b = omt.BatchSolver(probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch = b.solve(a.cap, tol, 64)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    its = [i["iters"] for i in batch]
+    same = all(p["iters"] == q["iters"] for p, q in zip(plain, batch))
+    cells = sum(sp["side"] ** 2 * i for sp, i in zip(specs, its))
+    return _line("time to 1e-5 relative residual, batched vs plain", t_plain / t_batch, "x", sum(its), 0,
+                 t_batch * 1e3 / max(its), {"workload": f"batched_{a.pairs}_pairs_side64-512_k1or3",
+                                            "pairs": a.pairs, "tol": tol, "check_every": 64,
+                                            "potential": "compensated FP32", "parallelism": "single-gpu"},
+                 batched_s=t_batch, plain_s=t_plain, converged=sum(i["converged"] for i in batch),
+                 same_iterations=same, iterations={"min": min(its), "median": sorted(its)[len(its) // 2],
+                                                   "max": max(its), "total": sum(its)},
+                 batched_cell_iter_per_s=cells / t_batch, plain_cell_iter_per_s=cells / t_plain)
+
+
+def bench_rgb(a):
+    """256x256, k=3 triangle, alpha in {0.5, 1, 4}: time to 1e-5 per pair."""
+    import torch
+    from paper_1712_10279_amd import inputs as I
+    from paper_1712_10279_amd import omt
+    tol = a.tol or 1e-5
+    out = []
+    total_t, total_it = 0.0, 0
+    for alpha in (0.5, 1.0, 4.0):
+        d = I.rgb_256(alpha)
+        s = omt.Solver(torch.as_tensor(d["rho0"], dtype=torch.float32, device="cuda"),
+                       torch.as_tensor(d["rho1"], dtype=torch.float32, device="cuda"), d["edges"], alpha=alpha,
+                       tau=I.tuned_tau(256, 256), compensated=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.solve(a.cap, tol, 64)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        total_t += dt
+        total_it += info["iters"]
+        out.append({"alpha": alpha, "seconds": dt, "iterations": info["iters"], "converged": info["converged"],
+                    "V": s.distance()[0], "rel_gap": info["rel_gap"]})
+    return _line("time to 1e-5 relative residual", total_t, "s", total_it, 0, total_t * 1e3 / total_it,
+                 {"workload": "vomt_256x256_k3_triangle_3alphas", "tol": tol, "potential": "compensated FP32",
+                  "tau": I.tuned_tau(256, 256), "parallelism": "single-gpu"}, pairs=out)
+
+
+def bench_loss(a):
+    """8 pairs of 512x512, k=3: forward to 1e-6 and backward (+-Phi)."""
+    import torch
+    from paper_1712_10279_amd import inputs as I
+    from paper_1712_10279_amd import omt
+    tol = a.tol or 1e-6
+    ds = [I.loss_512(q) for q in range(8)]
+    r0 = torch.stack([torch.as_tensor(d["rho0"], dtype=torch.float32, device="cuda") for d in ds]).requires_grad_(True)
+    r1 = torch.stack([torch.as_tensor(d["rho1"], dtype=torch.float32, device="cuda") for d in ds])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    V = omt.omt_loss(r0, r1, I.TRIANGLE, max_iters=a.cap, tol=tol, tau=I.tuned_tau(512, 512), compensated=True)
+    V.sum().backward()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return _line("forward+backward time, 8 pairs to 1e-6", dt, "s", 8, 0, dt * 1e3 / 8,
+                 {"workload": "loss_8x512x512_k3_triangle", "tol": tol, "potential": "compensated FP32",
+                  "parallelism": "single-gpu"}, V=[float(v) for v in V.detach().cpu()])
+
+
 def main():
     a = _parse()
     if a.copy_calibration:
         copy_calibration(a.copy_calibration)
+        return
+    if a.workload != "large":
+        if a.gpus != 1:
+            print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus})", file=sys.stderr)
+            sys.exit(2)
+        fn = {"batched": bench_batched, "rgb": bench_rgb, "loss": bench_loss}[a.workload]
+        print(json.dumps(fn(a)), flush=True)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {a.gpus})",

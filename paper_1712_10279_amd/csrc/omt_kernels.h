@@ -68,6 +68,7 @@ struct StepLaunch {
 // Defined once per channel count in step.hip (compiled per channel count).
 hipError_t launch_step(const StepLaunch &L);
 bool step_supported(int dtype, int k, int gk, int lb, int T, bool comp);
+hipError_t step_blocks_per_cu(const StepLaunch &L, int *blocks);  // resident workgroups per CU
 // Per-tile metrics of the step args' (in -> out) buffers into partials
 // [ntiles][NMET]; tiles are 64 columns x 16 rows.
 hipError_t launch_tile_metrics(const StepLaunch &L, int ncolw, int ntiles, double *partials);

@@ -73,6 +73,33 @@ hipError_t launch_one(const StepLaunch &Lc)
     return hipGetLastError();
 }
 
+template <typename R, int GK, int L, int T, bool COMP>
+hipError_t occ_one(int *blocks)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, pdhg_step_kernel<R, OMT_K, GK, L, T, COMP>,
+                                                         WAVE * STEP_WAVES_PER_WG, 0);
+}
+
+template <int GK, int L>
+hipError_t occ_T(const StepLaunch &Lc, int *blocks)
+{
+    if (Lc.dtype == 1) return occ_one<double, GK, L, 1, false>(blocks);
+    if (Lc.T == 1) return Lc.comp ? occ_one<float, GK, L, 1, true>(blocks) : occ_one<float, GK, L, 1, false>(blocks);
+    if constexpr (GK != G_DENSE) {
+        switch (Lc.T) {
+            case 2: return Lc.comp ? occ_one<float, GK, L, 2, true>(blocks) : occ_one<float, GK, L, 2, false>(blocks);
+#if OMT_K <= 5
+            case 4: return Lc.comp ? occ_one<float, GK, L, 4, true>(blocks) : occ_one<float, GK, L, 4, false>(blocks);
+#endif
+#if OMT_K <= 3
+            case 8: return Lc.comp ? occ_one<float, GK, L, 8, true>(blocks) : occ_one<float, GK, L, 8, false>(blocks);
+#endif
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename R, int GK, int L, bool COMP>
 hipError_t launch_met(const StepLaunch &Lc, int ncolw, int ntiles, double *partials)
 {
@@ -150,6 +177,20 @@ hipError_t OMT_CAT(launch_metrics_k, OMT_K)(const StepLaunch &Lc, int ncolw, int
     if (Lc.gk == G_COMPLETE && Lc.lb == L_FULL) return dispatch_met<G_COMPLETE, L_FULL>(Lc, ncolw, ntiles, partials);
     if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return dispatch_met<G_DENSE, L_TREE>(Lc, ncolw, ntiles, partials);
     if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return dispatch_met<G_DENSE, L_FULL>(Lc, ncolw, ntiles, partials);
+#endif
+    return hipErrorInvalidValue;
+}
+
+hipError_t OMT_CAT(step_blocks_per_cu_k, OMT_K)(const StepLaunch &Lc, int *blocks)
+{
+    if (Lc.gk == G_NONE && Lc.lb == 0) return occ_T<G_NONE, 0>(Lc, blocks);
+#if OMT_K >= 2
+    if (Lc.gk == G_PATH && Lc.lb == L_TREE) return occ_T<G_PATH, L_TREE>(Lc, blocks);
+#endif
+#if OMT_K >= 3
+    if (Lc.gk == G_COMPLETE && Lc.lb == L_FULL) return occ_T<G_COMPLETE, L_FULL>(Lc, blocks);
+    if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return occ_T<G_DENSE, L_TREE>(Lc, blocks);
+    if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return occ_T<G_DENSE, L_FULL>(Lc, blocks);
 #endif
     return hipErrorInvalidValue;
 }

@@ -40,6 +40,13 @@ def default_tau(m: int, n: int) -> float:
     return 1.0 if max(m, n) <= 64 else 3.0
 
 
+def tuned_tau(m: int, n: int) -> float:
+    """Dual step for the time-to-tolerance workloads (the paper tunes tau for
+    the fastest convergence): grows with the grid side because the cell
+    masses, and so the per-iteration dual increments, shrink with the grid."""
+    return max(1.0, max(m, n) / 8.0)
+
+
 def gaussian_mixture(m: int, n: int, k: int, bumps: int, sig_lo: float, sig_hi: float,
                      floor: float, rng: np.random.Generator, channel_mass=None) -> np.ndarray:
     """(m, n, k) float64 cell masses, unit total mass."""

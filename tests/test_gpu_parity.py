@@ -244,3 +244,25 @@ def test_distance_of_equal_densities_is_zero():
     info = s.solve(500, 0.0, 64)
     assert s.distance()[0] == 0.0
     assert info["residual"] == 0.0
+
+
+def test_graph_replay_and_autotune_do_not_change_bits(monkeypatch):
+    """Check intervals replayed as HIP graphs, and the autotuned launch shape,
+    give the same iterates as plain launches."""
+    torch = cuda()
+    r0, r1 = I.random_pair(32, 120, 150, 3)
+    monkeypatch.setenv("OMT_NO_GRAPH", "1")
+    a = _solver(torch, r0, r1, I.TRIANGLE, "f32", tau=3.0)
+    ia = a.solve(640, 0.0, 64)
+    monkeypatch.delenv("OMT_NO_GRAPH")
+    b = _solver(torch, r0, r1, I.TRIANGLE, "f32", tau=3.0)
+    ib = b.solve(640, 0.0, 64)
+    c = _solver(torch, r0, r1, I.TRIANGLE, "f32", tau=3.0)
+    T, rows, us = c.autotune(32)
+    note(f"autotune: T {T} rows {rows} {us:.2f} us/iteration")
+    assert T in (1, 2, 4, 8) and rows >= 1 and us > 0
+    ic = c.solve(640, 0.0, 64)
+    sa, sb, sc = a.get_state(), b.get_state(), c.get_state()
+    for key in ("phi", "u", "w"):
+        assert torch.equal(sa[key], sb[key]) and torch.equal(sa[key], sc[key]), key
+    assert ia["residual"] == ib["residual"] == ic["residual"]
