@@ -64,7 +64,7 @@ def copy_calibration(mib):
 
 def _kernel_hash():
     h = hashlib.sha256()
-    for f in ("step.hip", "omt_kernels.h"):
+    for f in ("step.hip", "step_device.h", "omt_kernels.h"):
         with open(os.path.join(ROOT, "paper_1712_10279_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

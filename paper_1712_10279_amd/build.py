@@ -43,9 +43,9 @@ def _units():
     return [u for u in units if os.path.exists(u[0])]
 
 
-def _compile(unit, verbose):
+def _compile(unit, verbose, defines=()):
     src, obj, extra = unit
-    cmd = [HIPCC] + COMMON + extra + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + COMMON + [f"-D{d}" for d in defines] + extra + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,26 +55,36 @@ def _compile(unit, verbose):
     return obj, warn
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    os.makedirs(OBJ, exist_ok=True)
-    units = _units()
+def build(verbose: bool = False, jobs: int | None = None, defines=(), out: str | None = None) -> str:
+    """Compile and link; ``defines`` are extra -D macros and ``out`` another
+    library path (for variants built side by side)."""
+    obj_dir = OBJ if not defines else OBJ + "_" + "_".join(d.replace("=", "") for d in defines)
+    os.makedirs(obj_dir, exist_ok=True)
+    units = [(src, os.path.join(obj_dir, os.path.basename(obj)), extra) for src, obj, extra in _units()]
     jobs = jobs or min(len(units), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        results = list(ex.map(lambda u: _compile(u, verbose), units))
+        results = list(ex.map(lambda u: _compile(u, verbose, defines), units))
     for obj, warn in results:
         if warn and verbose:
             print(f"[{os.path.basename(obj)}] {warn}", flush=True)
     objs = [r[0] for r in results]
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    lib = out or LIB
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", lib + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":
+    import argparse
     import time
+    ap = argparse.ArgumentParser()
+    ap.add_argument("-v", action="store_true")
+    ap.add_argument("-D", action="append", default=[], help="extra macro, e.g. -D OMT_STREAM_NT=1")
+    ap.add_argument("-o", default=None, help="library path (default: the package's libomt.so)")
+    args = ap.parse_args()
     t0 = time.time()
-    build(verbose="-v" in sys.argv)
-    print(f"built {LIB} in {time.time() - t0:.1f} s")
+    path = build(verbose=args.v, defines=args.D, out=args.o)
+    print(f"built {path} in {time.time() - t0:.1f} s")

@@ -14,6 +14,27 @@ __device__ __forceinline__ float lane_prev(float v) { return __shfl_up(v, 1u, WA
 __device__ __forceinline__ double lane_next(double v) { return __shfl_down(v, 1u, WAVE); }
 __device__ __forceinline__ double lane_prev(double v) { return __shfl_up(v, 1u, WAVE); }
 
+// Streamed fields (u, w, f read once per pass; all outputs written once) may
+// carry the non-temporal hint so that they do not displace the potential
+// rows that neighbouring waves still read.  Off unless OMT_STREAM_NT is set.
+#ifndef OMT_STREAM_NT
+#define OMT_STREAM_NT 0
+#endif
+template <typename R>
+__device__ __forceinline__ R ld_stream(const R *p)
+{
+    if constexpr (OMT_STREAM_NT != 0) return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <typename R>
+__device__ __forceinline__ void st_stream(R *p, R v)
+{
+    if constexpr (OMT_STREAM_NT != 0)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // value of lane L (a wave-uniform result)
 __device__ __forceinline__ float lane_get(float v, int L)
 {
@@ -157,7 +178,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
             if (!lane_ok) wt[e] = R(0);
             wO[e] = wt[e];
             wb[e] = R(2) * wt[e] - w[e];
-            if (st && e < a.l) a.w_out[e * P + o] = wt[e];
+            if (st && e < a.l) st_stream(&a.w_out[e * P + o], wt[e]);
         }
     }
 
@@ -280,10 +301,10 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         uxO[c] = bx;
         uyO[c] = by;
         if (st) {
-            a.phi_out[c * P + o] = po;
+            st_stream(&a.phi_out[c * P + o], po);
             if (COMP) a.plo_out[c * P + o] = float(pol);
-            a.u_out[c * P + o] = bx;
-            a.u_out[(K + c) * P + o] = by;
+            st_stream(&a.u_out[c * P + o], bx);
+            st_stream(&a.u_out[(K + c) * P + o], by);
         }
     }
 }
@@ -355,12 +376,12 @@ __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int 
         const bool full = !ALN || r >= i0;
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-            nux[c] = jin ? uin[c * P + o] : R(0);
-            nuy[c] = jin ? uin[(K + c) * P + o] : R(0);
-            nf[c] = (jin && full) ? fin[c * P + o] : R(0);
+            nux[c] = jin ? ld_stream(&uin[c * P + o]) : R(0);
+            nuy[c] = jin ? ld_stream(&uin[(K + c) * P + o]) : R(0);
+            nf[c] = (jin && full) ? ld_stream(&fin[c * P + o]) : R(0);
         }
 #pragma unroll
-        for (int e = 0; e < LA; ++e) nw[e] = (L > 0 && jin && full && e < a.l) ? win[e * P + o] : R(0);
+        for (int e = 0; e < LA; ++e) nw[e] = (L > 0 && jin && full && e < a.l) ? ld_stream(&win[e * P + o]) : R(0);
     };
     auto load_edges_first = [&](int r) {
         if (hasR && hl) {

@@ -14,7 +14,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libomt.so")
+# OMT_LIB selects another build of the same library (e.g. a variant built
+# with different compile-time options); the default is the in-tree build.
+LIB_PATH = os.environ.get("OMT_LIB", os.path.join(_HERE, "libomt.so"))
 
 OK, EINVAL, EGRAPH, EMASS, ESTEP, ENOMEM, EDEVICE, ENOTCONV, EDIVERGED, EUNSUPPORTED = range(10)
 U_L12, U_L1, U_L2 = 0, 1, 2
