@@ -35,7 +35,7 @@ class _Problem(C.Structure):
                 ("edges", _ip), ("cost", _dp),
                 ("alpha", C.c_double), ("tau", C.c_double), ("mu", C.c_double),
                 ("nu", C.c_double), ("h", C.c_double),
-                ("unorm", C.c_int), ("wnorm", C.c_int)]
+                ("unorm", C.c_int), ("wnorm", C.c_int), ("eps", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -91,6 +91,7 @@ class Problem:
     h: float = 0.0
     unorm: int = U_L12
     wnorm: int = W_L1
+    eps: float = 0.0
 
     def __post_init__(self):
         self.edges = np.ascontiguousarray(np.asarray(self.edges, dtype=np.int32).reshape(-1, 2))
@@ -105,7 +106,7 @@ class Problem:
 
     def _c(self) -> _Problem:
         return _Problem(self.m, self.n, self.k, self.l, _i(self.edges), _d(self.cost),
-                        self.alpha, self.tau, self.mu, self.nu, self.h, self.unorm, self.wnorm)
+                        self.alpha, self.tau, self.mu, self.nu, self.h, self.unorm, self.wnorm, self.eps)
 
     def _fill_steps(self):
         p = self._c()
@@ -281,12 +282,12 @@ def potential(phi, edges):
 
 
 def solve_pair(rho0, rho1, edges, alpha=1.0, tau=1.0, cost=None, unorm=U_L12, wnorm=W_L1,
-               max_iters=1000, tol=0.0, check_every=64, h=0.0, mu=0.0, nu=0.0):
+               max_iters=1000, tol=0.0, check_every=64, h=0.0, mu=0.0, nu=0.0, eps=0.0):
     """Convenience: problem set-up + f + solve from zeros."""
     rho0 = _f64(rho0)
     m, n, k = rho0.shape
     p = Problem(m, n, k, edges=edges, cost=cost, alpha=alpha, tau=tau, h=h, mu=mu, nu=nu,
-                unorm=unorm, wnorm=wnorm)
+                unorm=unorm, wnorm=wnorm, eps=eps)
     f, _ = prepare_f(rho0, rho1, p.edges)
     r = solve(p, f, max_iters, tol, check_every)
     r["problem"] = p

@@ -26,6 +26,10 @@
  *     class (connected component of the channel graph) removed in FP64.
  *   - the relative residual is sqrt(R^k / R^0) with R^0 = tau ||f||^2, the
  *     value of R for the first step taken from the all-zero start.
+ *   - quadratic regularisation (Sec. 9) adds eps (|u|^2 + |w|^2) with the
+ *     Euclidean square of all components, so each shrink result is divided
+ *     by 1 + 2 t eps (t the step of that block): the prox of
+ *     t ||.|| + t eps |.|^2.
  *
  * Layout (paper order): arrays indexed [i][j][c], channel fastest:
  *   phi, lambda, f, u_x, u_y : m*n*k      w : m*n*l
@@ -48,6 +52,7 @@ typedef struct {
     const double *cost;  /* l edge costs c_e > 0                            */
     double alpha, tau, mu, nu, h;
     int unorm, wnorm;
+    double eps;          /* quadratic regularisation weight (Sec. 9), >= 0  */
 } orc_problem;
 
 typedef struct {
@@ -422,6 +427,11 @@ static void pdhg_step(const orc_problem *p, const double *f, const double *phi, 
             by[c] = uy[q * (size_t)k + c] + p->mu * W->gy[q * (size_t)k + c];
         }
         orc_shrink_u(p->unorm, k, bx, by, p->mu);
+        if (p->eps > 0.0)
+            for (int c = 0; c < k; ++c) {
+                bx[c] /= 1.0 + 2.0 * p->mu * p->eps;
+                by[c] /= 1.0 + 2.0 * p->mu * p->eps;
+            }
     }
 
     if (l > 0) {
@@ -430,6 +440,8 @@ static void pdhg_step(const orc_problem *p, const double *f, const double *phi, 
             double *b = w1 + q * (size_t)l;
             for (int e = 0; e < l; ++e) b[e] = w[q * (size_t)l + e] + p->nu * W->gG[q * (size_t)l + e];
             orc_shrink_w(p->wnorm, l, b, p->alpha * p->nu);
+            if (p->eps > 0.0)
+                for (int e = 0; e < l; ++e) b[e] /= 1.0 + 2.0 * p->nu * p->eps;
         }
     }
 
@@ -450,7 +462,8 @@ static void pdhg_step(const orc_problem *p, const double *f, const double *phi, 
 /* --------------------------------------------------------------- metrics */
 
 /* Quantities reported at a check: out[0] = R^k (Sec. 6.1, with 1/nu on the
- * second block), out[1] = primal objective, out[2] = dual objective <phi1,f>,
+ * second block), out[1] = primal objective (with the regulariser), out[2] =
+ * <phi1, f> (the dual objective when eps = 0),
  * out[3] = ||div_x u1 + div_G w1 + f||^2, out[4] = ||f||^2. */
 void orc_metrics(const orc_problem *p, const double *f, const double *phi, const double *ux, const double *uy,
                  const double *w, const double *phi1, const double *ux1, const double *uy1, const double *w1,
@@ -482,6 +495,12 @@ void orc_metrics(const orc_problem *p, const double *f, const double *phi, const
     for (size_t q = 0; q < P; ++q) {
         prim += orc_norm_u(p->unorm, k, ux1 + q * (size_t)k, uy1 + q * (size_t)k);
         if (l > 0) prim += p->alpha * orc_norm_w(p->wnorm, l, w1 + q * (size_t)l);
+    }
+    if (p->eps > 0.0) {
+        double sq = 0.0;
+        for (size_t q = 0; q < Pk; ++q) sq += ux1[q] * ux1[q] + uy1[q] * uy1[q];
+        for (size_t q = 0; q < Pl; ++q) sq += w1[q] * w1[q];
+        prim += p->eps * sq;
     }
     orc_div_x(m, n, k, p->h, ux1, uy1, t1);
     if (l > 0) orc_div_G(m, n, k, l, p->edges, p->cost, w1, t2);

@@ -10,6 +10,7 @@ typedef struct {
     const double *cost;
     double alpha, tau, mu, nu, h;
     int unorm, wnorm;
+    double eps;
 } orc_problem;
 typedef struct {
     int64_t iters;
@@ -50,7 +51,7 @@ int main(void)
                 sb += b[q];
             }
             for (size_t q = 0; q < P * k; ++q) b[q] *= sa / sb;
-            orc_problem p = {m, n, k, l, tri, cost, 0.7, 1.0, 0.0, 0.0, 0.0, unorm, unorm % 2};
+            orc_problem p = {m, n, k, l, tri, cost, 0.7, 1.0, 0.0, 0.0, 0.0, unorm, unorm % 2, 0.1 * unorm};
             orc_default_steps(&p);
             orc_prepare_f(m, n, k, l, tri, a, b, f);
             orc_info info;

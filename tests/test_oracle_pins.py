@@ -206,3 +206,37 @@ def test_gradient_convexity_sandwich(orc):
         lo, hi = (base["primal"] - vm) / delta, (vp - base["primal"]) / delta
         slack = 1e-6
         assert lo - slack <= g <= hi + slack
+
+
+@pytest.mark.parametrize("unorm", [0, 1, 2])
+def test_regularised_strips_closed_form(orc, unorm):
+    # Quadratic regularisation (Sec. 9), eps sum |u|^2: for strips the row sums
+    # of u_x are forced (h F_i), and both |.| and |.|^2 are smallest with the
+    # flux spread evenly over the n columns and u_y = 0, so
+    # V_eps = h sum |F_i| + eps h^2 sum F_i^2 / n exactly.
+    m, n = 9, 6
+    rng = np.random.default_rng(8)
+    a, b = rng.random(m) + 0.1, rng.random(m) + 0.1
+    r0 = np.repeat(a[:, None], n, 1)[:, :, None]
+    r1 = np.repeat(b[:, None], n, 1)[:, :, None]
+    r0 /= r0.sum()
+    r1 /= r1.sum()
+    h = 1.0 / (max(m, n) - 1)
+    F = np.cumsum((r0 - r1).sum(axis=(1, 2)))[:-1]
+    eps = 3.0
+    V = h * np.abs(F).sum() + eps * h * h * (F ** 2).sum() / n
+    r = orc.solve_pair(r0, r1, np.zeros((0, 2)), unorm=unorm, eps=eps, max_iters=400000, tol=1e-11)
+    assert r["primal"] == pytest.approx(V, rel=1e-9)
+    ux = r["state"]["ux"][:-1, :, 0]
+    assert np.allclose(ux, (h * F / n)[:, None], atol=1e-9)
+    assert np.abs(r["state"]["uy"]).max() < 1e-9
+
+
+def test_regularisation_vanishes_as_eps_goes_to_zero(orc):
+    r0, r1 = I.random_pair(9, 8, 9, 3)
+    base = _solve(orc, r0, r1, I.TRIANGLE, tol=1e-11)["primal"]
+    vals = [orc.solve_pair(r0, r1, I.TRIANGLE, eps=e, max_iters=400000, tol=1e-11)["primal"] for e in (1e-1, 1e-2, 1e-3)]
+    gaps = [v - base for v in vals]
+    assert all(g >= -1e-10 for g in gaps)
+    assert gaps[0] > gaps[1] > gaps[2]
+    assert gaps[2] < 1e-3 * base
