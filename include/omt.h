@@ -97,14 +97,17 @@ typedef struct {
     uint32_t flags;            /* OMT_FLAG_* */
     int32_t tblock;            /* iterations fused per pass over HBM (1, 2, 4, 8); 0 = tuned default */
     int32_t rows_per_wave;     /* rows one wavefront streams through; 0 = tuned default */
+    double reg_eps;            /* >= 0: quadratic regularisation eps (|u|^2 + |w|^2), Euclidean squares of
+                                  all components (Sec. 9); each shrink is then divided by 1 + 2 t eps with
+                                  t = mu for u and nu for w.  0 gives the method of Sec. 7.2 exactly. */
 } omt_params;
 
 typedef struct {
     int64_t iters;          /* iterations done by the solve */
     double residual;        /* sqrt(R^k / R^0), R^k the fixed-point residual of Sec. 6.1 for the last
                                step (with 1/nu on the w block) and R^0 = tau ||rho1 - rho0||^2 */
-    double primal;          /* ||u||_u + alpha ||w||_w at the last iterate */
-    double dual;            /* <phi, rho1 - rho0> at the last iterate */
+    double primal;          /* ||u||_u + alpha ||w||_w (+ eps (|u|^2 + |w|^2)) at the last iterate */
+    double dual;            /* <phi, rho1 - rho0> at the last iterate (the dual objective when eps = 0) */
     double rel_gap;         /* (primal - dual) / primal, the precision measure of Sec. 8.1 */
     double mass_residual;   /* ||div_x u + div_G w + rho1 - rho0|| / ||rho1 - rho0|| */
     double R;               /* R^k itself */

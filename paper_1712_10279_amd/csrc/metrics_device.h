@@ -7,7 +7,7 @@
 // objectives):
 //   v[0] = |u' - u|^2             v[1] = |w' - w|^2        v[2] = |phi' - phi|^2
 //   v[3] = <phi' - phi, div_x(u' - u) + div_G(w' - w)>
-//   v[4] = ||u'||_u + alpha ||w'||_w                        (primal objective)
+//   v[4] = ||u'||_u + alpha ||w'||_w (+ eps (|u'|^2 + |w'|^2))  (primal objective)
 //   v[5] = <phi', f>                                         (dual objective)
 //   v[6] = |div_x u' + div_G w' + f|^2                       (constraint residual)
 //   v[7] = sum of phi'
@@ -44,7 +44,7 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             we0[e] = on ? double(w0[e * P + o]) : 0.0;
             we1[e] = on ? double(w1[e * P + o]) : 0.0;
         }
-        double u2 = 0.0;
+        double u2 = 0.0, sq = 0.0;
 #pragma unroll
         for (int c = 0; c < K; ++c) {
             double p0 = double(phi0[c * P + o]), p1 = double(phi1[c * P + o]);
@@ -92,6 +92,7 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             const double r = (div1 - dg1) + fc;
             v[6] += r * r;
             v[7] += p1;
+            sq += ux1 * ux1 + uy1 * uy1;
             if (a.unorm == 0)
                 v[4] += sqrt(ux1 * ux1 + uy1 * uy1);
             else if (a.unorm == 1)
@@ -108,6 +109,7 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             w2 += we1[e] * we1[e];
         }
         v[4] += a.alpha * (a.wnorm == 0 ? wn : sqrt(w2));
+        if (a.eps > 0.0) v[4] += a.eps * (sq + w2);  // quadratic regularisation
     }
 }
 

@@ -183,7 +183,7 @@ struct Resolved {
     int m, n, k, l, gk, lb;
     std::vector<int32_t> edges;
     std::vector<double> cost;
-    double alpha, tau, mu, nu, h, lmax;
+    double alpha, tau, mu, nu, h, lmax, eps;
     int unorm, wnorm, dtype;
     bool comp;
     int tblock, rows;
@@ -209,6 +209,7 @@ omt_status resolve(const omt_params *p, Resolved &r)
     if (p->wnorm < 0 || p->wnorm > 1) return fail(OMT_EINVAL, "unknown w norm %d", p->wnorm);
     if (p->dtype != OMT_F32 && p->dtype != OMT_F64) return fail(OMT_EINVAL, "unknown dtype %d", p->dtype);
     if (p->tblock < 0 || p->rows_per_wave < 0) return fail(OMT_EINVAL, "tblock and rows_per_wave must be >= 0");
+    if (!(p->reg_eps >= 0.0) || !std::isfinite(p->reg_eps)) return fail(OMT_EINVAL, "reg_eps must be finite and >= 0");
 
     r.m = p->m;
     r.n = p->n;
@@ -252,6 +253,7 @@ omt_status resolve(const omt_params *p, Resolved &r)
     }
     r.alpha = p->alpha;
     r.tau = p->tau;
+    r.eps = p->reg_eps;
     r.unorm = p->unorm;
     r.wnorm = p->wnorm;
     r.dtype = p->dtype;
@@ -425,6 +427,9 @@ void fill_args(StepArgs<R> &a, const omt_ctx *h, int ci, int co, int wi, int wo,
     a.tau = R(r.tau);
     a.inv_h = R(1.0 / r.h);
     a.alpha = r.alpha;
+    a.eps = r.eps;
+    a.ureg = R(1.0 / (1.0 + 2.0 * r.mu * r.eps));
+    a.wreg = R(1.0 / (1.0 + 2.0 * r.nu * r.eps));
     for (int q = 0; q < KMAX * LMAX; ++q) a.gm[q] = R(0);
     for (int q = 0; q < LMAX; ++q) a.ic[q] = R(0);
     for (int e = 0; e < r.l; ++e) {

@@ -50,7 +50,9 @@ struct StepArgs {
     R mu, mu_h;            // mu, mu / h
     R nu, anu;             // nu, alpha nu
     R tau, inv_h;          // tau, 1 / h
+    R ureg, wreg;          // 1 / (1 + 2 mu eps), 1 / (1 + 2 nu eps): regularised shrinks (1 without)
     double alpha;          // weight of the transfer term (objective)
+    double eps;            // quadratic regularisation weight (objective)
     R ic[LMAX];            // 1 / c_e
     R gm[KMAX * LMAX];     // dense graphs: M = D diag(1/c), row c, column e at gm[c * LMAX + e]
 };

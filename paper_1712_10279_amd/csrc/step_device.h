@@ -175,6 +175,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         shrink_w<R, LA>(a.wnorm, wt, a.anu);
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
+            wt[e] = wt[e] * a.wreg;  // regularised prox (factor 1 without regularisation)
             if (!lane_ok) wt[e] = R(0);
             wO[e] = wt[e];
             wb[e] = R(2) * wt[e] - w[e];
@@ -257,6 +258,8 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         R tx, ty, bx, by;
         utilde(c, tx, ty);
         shrink_pair(tx, ty, s_all, bx, by);
+        bx = bx * a.ureg;  // regularised prox (factor 1 without regularisation)
+        by = by * a.ureg;
         if (!lane_ok) bx = by = R(0);
         const R ubx = R(2) * bx - ux[c];
         const R uby = R(2) * by - uy[c];
@@ -265,6 +268,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
             R ex, ey, ebx, eby;
             utilde_left(c, ex, ey);
             shrink_pair(ex, ey, s_left, ebx, eby);
+            eby = eby * a.ureg;
             const R el = E.hasL ? R(2) * eby - lane_get(E.Luy, c) : R(0);
             if (lane == 0) ubl = el;
         }

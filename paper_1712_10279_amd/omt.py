@@ -31,7 +31,8 @@ class Params(C.Structure):
                 ("edges", C.POINTER(C.c_int32)), ("edge_cost", C.POINTER(C.c_double)),
                 ("alpha", C.c_double), ("tau", C.c_double), ("mu", C.c_double), ("nu", C.c_double),
                 ("h", C.c_double), ("unorm", C.c_int32), ("wnorm", C.c_int32), ("dtype", C.c_int32),
-                ("flags", C.c_uint32), ("tblock", C.c_int32), ("rows_per_wave", C.c_int32)]
+                ("flags", C.c_uint32), ("tblock", C.c_int32), ("rows_per_wave", C.c_int32),
+                ("reg_eps", C.c_double)]
 
 
 class Info(C.Structure):
@@ -131,6 +132,7 @@ class Config:
     compensated: bool = False
     tblock: int = 0
     rows_per_wave: int = 0
+    eps: float = 0.0
 
 
 def make_params(m, n, k, edges, cfg: Config, dtype: int):
@@ -148,6 +150,7 @@ def make_params(m, n, k, edges, cfg: Config, dtype: int):
     p.unorm, p.wnorm, p.dtype = int(cfg.unorm), int(cfg.wnorm), int(dtype)
     p.flags = FLAG_COMPENSATED_PHI if cfg.compensated else 0
     p.tblock, p.rows_per_wave = int(cfg.tblock), int(cfg.rows_per_wave)
+    p.reg_eps = float(cfg.eps)
     return p, (e, cost)
 
 

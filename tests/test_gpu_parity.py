@@ -266,3 +266,17 @@ def test_graph_replay_and_autotune_do_not_change_bits(monkeypatch):
     for key in ("phi", "u", "w"):
         assert torch.equal(sa[key], sb[key]) and torch.equal(sa[key], sc[key]), key
     assert ia["residual"] == ib["residual"] == ic["residual"]
+
+
+@pytest.mark.parametrize("unorm,wnorm", [(0, 0), (2, 1)])
+def test_fp64_regularised_matches_oracle(unorm, wnorm):
+    """Quadratic regularisation (Sec. 9): the GPU follows the oracle's
+    regularised iterates element by element."""
+    torch = cuda()
+    r0, r1 = I.random_pair(33, 40, 75, 3)
+    note(f"case: fp64 regularised eps=2 u{unorm} w{wnorm}")
+    r = oracle_run(r0, r1, I.TRIANGLE, 400, alpha=0.8, unorm=unorm, wnorm=wnorm, eps=2.0)
+    s = _solver(torch, r0, r1, I.TRIANGLE, "f64", alpha=0.8, unorm=unorm, wnorm=wnorm, eps=2.0)
+    info = s.solve(400, 0.0, 64)
+    _cmp_state(gpu_state_np(s), r, 1e-10, "regularised")
+    assert abs(info["primal"] - r["primal"]) <= 1e-10 * r["primal"]
