@@ -51,6 +51,7 @@ def test_step_sizes_follow_the_rule():
     ([(0, 1)], {"unorm": 7}, omt.EINVAL),
     ([(0, 1)], {"mu": 1.0}, omt.ESTEP),          # violates tau mu 8/h^2 + tau nu lmax < 1
     ([(0, 1)], {"nu": 10.0}, omt.ESTEP),
+    ([(0, 1)], {"eps": -1.0}, omt.EINVAL),       # regularisation weight must be >= 0
 ])
 def test_invalid_parameters(edges, kw, status):
     with pytest.raises(omt.OMTError) as e:
