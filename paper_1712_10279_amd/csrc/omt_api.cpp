@@ -386,7 +386,8 @@ struct omt_ctx {
     hipStream_t cap;           // private stream for capturing the check interval
     struct Graph {
         hipGraphExec_t exec;
-        int K, T, rowsT, rows1, cur, wcur;
+        int K, T, rowsT, rows1, cur, wcur;  // what it was captured for
+        int cur_after, wcur_after;          // buffer roles after one replay
     } graphs[2];
     int ngraphs;
 };
@@ -671,9 +672,10 @@ omt_status enqueue_interval(omt_ctx *h, int64_t nblk, int T, int rowsT, int rows
     return run_metrics(h, oc, h->cur, ow, h->wcur, stream);
 }
 
-// A full check interval replayed as one HIP graph (captured on first use
-// for the current buffer roles; two roles alternate because K is even and w
-// flips once per interval).
+// A full check interval replayed as one HIP graph, captured on first use for
+// the current buffer roles.  Every interval permutes the roles the same way
+// (each launch swaps phi/u, each out-of-place launch swaps w), so at most two
+// role sets alternate and two graphs cover a solve.
 omt_status graph_interval(omt_ctx *h, int K, int T, int rowsT, int rows1)
 {
     omt_ctx::Graph *g = nullptr;
@@ -695,6 +697,9 @@ omt_status graph_interval(omt_ctx *h, int K, int T, int rowsT, int rows1)
         HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
         omt_status s = enqueue_interval(h, K, T, rowsT, rows1, h->cap);
         hipError_t e = hipStreamEndCapture(h->cap, &graph);
+        // capturing ran nothing: note where the launches leave the buffer
+        // roles, then put the handle back
+        const int c1 = h->cur, w1 = h->wcur;
         h->cur = c0;
         h->wcur = w0;
         h->iters_done = it0;
@@ -710,6 +715,8 @@ omt_status graph_interval(omt_ctx *h, int K, int T, int rowsT, int rows1)
         ng.rows1 = rows1;
         ng.cur = c0;
         ng.wcur = w0;
+        ng.cur_after = c1;
+        ng.wcur_after = w1;
         e = hipGraphInstantiateWithFlags(&ng.exec, graph, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(OMT_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
@@ -718,8 +725,8 @@ omt_status graph_interval(omt_ctx *h, int K, int T, int rowsT, int rows1)
     }
     HIP_TRY(hipGraphLaunch(g->exec, h->cap));
     // the replay moves the buffers exactly as the captured launches did
-    h->cur = (c0 + K) & 1;
-    h->wcur = 1 - w0;
+    h->cur = g->cur_after;
+    h->wcur = g->wcur_after;
     h->iters_done = it0 + K;
     return read_results(h, NMET, h->cap);
 }
@@ -877,9 +884,8 @@ omt_status omt_solve(omt_handle h, int64_t max_iters, double tol, int32_t check_
     omt_status s = OMT_OK;
     int64_t it = 0;
     const int rowsT = default_rows(h, T), rows1 = default_rows(h, 1);
-    // full intervals are replayed as graphs when the library may use them
-    // (OMT_NO_GRAPH unset) and K is even, so that buffer roles repeat
-    const bool use_graph = K % 2 == 0 && K >= 8 && !std::getenv("OMT_NO_GRAPH");
+    // full intervals are replayed as graphs unless OMT_NO_GRAPH is set
+    const bool use_graph = K >= 8 && !std::getenv("OMT_NO_GRAPH");
     if (use_graph) HIP_TRY(hipStreamSynchronize(h->stream));
     while (it < max_iters) {
         const int64_t nblk = std::min<int64_t>(K, max_iters - it);
