@@ -1382,7 +1382,11 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         destroy_batch(h);
         return fail(OMT_EDEVICE, "batched kernel does not fit on a compute unit");
     }
-    h->nblocks = bpc * cus;  // every workgroup resident at once
+    // every workgroup resident at once, and no more workgroups than the
+    // strips keep busy (about two strips per wave): fewer workgroups make the
+    // grid barriers cheaper for small batches
+    const int want = (h->total_tiles + 2 * STEP_WAVES_PER_WG - 1) / (2 * STEP_WAVES_PER_WG);
+    h->nblocks = std::max(1, std::min(bpc * cus, want));
     // remember the rows per strip in the per-problem arguments
     for (int p = 0; p < B; ++p) h->ctx[p]->r.rows = L.rows[p];
     *out = h;
