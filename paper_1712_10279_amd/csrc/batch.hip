@@ -29,21 +29,34 @@ __device__ __forceinline__ unsigned ld_acq(const unsigned *p)
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide barrier over nblocks resident workgroups: bar[0] arrivals,
-// bar[1] generation, bar[2] abort flag.  Returns true if the barrier was
-// abandoned (abort flag set).
+// Grid-wide barrier over nblocks resident workgroups, in two levels so that
+// no counter sees more than a few dozen arrivals: workgroups meet in 8
+// groups (blockIdx mod 8, which is also how workgroups are dealt to the
+// XCDs), the last of each group meets the others at the top.  Words of bar:
+// [0] top arrivals, [1] generation, [2] abort flag, [3] problems stopped,
+// [BAR_GROUP0 + BAR_STRIDE g] arrivals of group g (own cache line).
+// Returns true if the barrier was abandoned (abort flag set).
 __device__ bool grid_sync(unsigned *bar, unsigned nblocks)
 {
     __shared__ int s_abort;
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
+        const unsigned G = nblocks < BAR_GROUPS ? nblocks : BAR_GROUPS;
+        const unsigned g = blockIdx.x % G;
+        const unsigned gsize = nblocks / G + (g < nblocks % G ? 1u : 0u);
         const unsigned gen = ld_acq(&bar[1]);
-        const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-        if (arrived == nblocks) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        unsigned *grp = &bar[BAR_GROUP0 + BAR_STRIDE * g];
+        bool released = false;
+        if (__hip_atomic_fetch_add(grp, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == gsize) {
+            __hip_atomic_store(grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == G) {
+                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released) {
             unsigned spins = 0;
             while (ld_acq(&bar[1]) == gen) {
                 if (ld_acq(&bar[2]) != 0u) break;

@@ -1274,7 +1274,7 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
     L.off_part = o;
     o += align256(sizeof(double) * NMET * size_t(L.total_mtiles));
     L.off_bar = o;
-    o += 256;
+    o += align256(sizeof(unsigned) * BAR_WORDS);
     L.total = o;
     return OMT_OK;
 }
@@ -1435,7 +1435,7 @@ omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, in
     hipGraphExec_t exec = nullptr;
     HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = launch_zero(h->d_state, sizeof(BatchPairState) * h->B, h->cap);
-    if (e == hipSuccess) e = launch_zero(h->d_bar, 256, h->cap);
+    if (e == hipSuccess) e = launch_zero(h->d_bar, sizeof(unsigned) * BAR_WORDS, h->cap);
     if (e == hipSuccess) e = launch_batch(ba, h->comp, h->nblocks, h->cap);
     hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {

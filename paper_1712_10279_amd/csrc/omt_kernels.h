@@ -102,11 +102,14 @@ struct BatchArgs {
     BatchPairState *state;
     const int *tile_pair, *mtile_pair;
     double *partials;
-    unsigned *bar;  // [0] arrivals, [1] generation, [2] abort, [3] problems stopped
+    unsigned *bar;  // barrier words, BAR_WORDS of them (see grid_sync in batch.hip)
     int B, total_tiles, total_mtiles, check_every;
     int64_t max_iters;
     double tol;
 };
+
+constexpr int BAR_GROUPS = 8, BAR_GROUP0 = 32, BAR_STRIDE = 32;
+constexpr int BAR_WORDS = BAR_GROUP0 + BAR_STRIDE * BAR_GROUPS;
 
 int batch_type(int k, int gk, int lb);  // -1 if not compiled into the batched kernel
 hipError_t batch_blocks_per_cu(bool comp, int *blocks);
