@@ -1,6 +1,9 @@
-// Persistent batched PDHG solver: many independent problems (different grid
-// sizes, channel counts and graphs) iterated together by one launch.
+// Batched PDHG solver: many independent problems (different grid sizes,
+// channel counts and graphs) iterated together.  Two schedules share the
+// per-strip and per-tile code: launches per iteration replayed as a graph
+// (the default, at the end of this file) and one persistent launch (below).
 //
+// Persistent launch:
 // The grid is sized to the number of workgroups the chip holds at once, so
 // every workgroup is resident, and it stays for the whole solve.  Each
 // iteration the waves walk the list of strips (64 columns x rows) of all
@@ -170,7 +173,112 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_kernel(const Ba
     }
 }
 
+// ------------------------------------------------ one launch per iteration
+//
+// The same work without grid barriers: one launch advances every unfinished
+// problem by one iteration (one wave per strip), a second launch computes the
+// metrics tiles at a check, and a third lets one wave per problem reduce its
+// tiles and take the stopping decision.  The host replays a check interval of
+// these launches as one HIP graph and reads back only the count of stopped
+// problems after each interval.
+
+__device__ __forceinline__ int remap_block(int b, int nwg)
+{
+    // contiguous tiles (one problem's strips) on one XCD: workgroups are
+    // dealt round-robin to the 8 XCDs
+    constexpr int NX = 8;
+    const int x = b % NX, idx = b / NX;
+    const int q = nwg / NX, r = nwg % NX;
+    return (x < r) ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
+}
+
+template <bool COMP>
+__global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_step_kernel(const BatchArgs ba, int var)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int t = remap_block(blockIdx.x, gridDim.x) * STEP_WAVES_PER_WG + threadIdx.x / WAVE;
+    if (t >= ba.total_tiles) return;
+    const int p = __builtin_amdgcn_readfirstlane(ba.tile_pair[t]);
+    if (ba.state[p].done) return;
+    const BatchPair &bp = ba.pairs[p];
+    const int local = t - bp.tile0;
+    strip_by_type<COMP>(bp.type, bp.v[var], local % bp.ncolw, local / bp.ncolw, lane);
+}
+
+template <bool COMP>
+__global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_metrics_kernel(const BatchArgs ba, int var)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int t = blockIdx.x * STEP_WAVES_PER_WG + threadIdx.x / WAVE;
+    if (t >= ba.total_mtiles) return;
+    const int p = __builtin_amdgcn_readfirstlane(ba.mtile_pair[t]);
+    if (ba.state[p].done) return;
+    const BatchPair &bp = ba.pairs[p];
+    const int local = t - bp.mtile0;
+    double v[NMET];
+    metrics_by_type<COMP>(bp.type, bp.v[var], local % bp.mcolw, local / bp.mcolw, lane, v);
+#pragma unroll
+    for (int q = 0; q < NMET; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) ba.partials[(int64_t)t * NMET + q] = s;
+    }
+}
+
+// One wave per problem: add up the tiles, count the iterations, decide.
+// last: this check follows the final iteration of the solve.
+__global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_decide_kernel(const BatchArgs ba, int iters,
+                                                                                 int last)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int p = blockIdx.x * STEP_WAVES_PER_WG + threadIdx.x / WAVE;
+    if (p >= ba.B) return;
+    BatchPairState &st = ba.state[p];
+    if (st.done) return;
+    const BatchPair &bp = ba.pairs[p];
+    reduce_tiles(ba.partials, bp.mtile0, bp.mtiles, lane, st.met);
+    if (lane == 0) {
+        const double *m = st.met;
+        const double R = m[0] / bp.mu + (bp.l > 0 ? m[1] / bp.nu : 0.0) + m[2] / bp.tau - 2.0 * m[3];
+        const bool conv = ba.tol > 0.0 && R <= ba.tol * ba.tol * bp.R0;
+        const bool bad = !isfinite(R) || !isfinite(m[4]);
+        st.iters += iters;
+        st.checks += 1;
+        st.cur = int(st.iters & 1);
+        st.wcur = st.checks & 1;
+        if (conv || bad || last) {
+            st.converged = conv ? 1 : 0;
+            st.done = 1;
+            atomicAdd(&ba.bar[3], 1u);
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_batch_step(const BatchArgs &a, bool comp, int var, hipStream_t s)
+{
+    const int nb = (a.total_tiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG;
+    if (comp)
+        hipLaunchKernelGGL(batch_step_kernel<true>, dim3(nb), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a, var);
+    else
+        hipLaunchKernelGGL(batch_step_kernel<false>, dim3(nb), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a, var);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_check(const BatchArgs &a, bool comp, int var, int iters, bool last, hipStream_t s)
+{
+    const int nb = (a.total_mtiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG;
+    if (comp)
+        hipLaunchKernelGGL(batch_metrics_kernel<true>, dim3(nb), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a, var);
+    else
+        hipLaunchKernelGGL(batch_metrics_kernel<false>, dim3(nb), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a, var);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nd = (a.B + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG;
+    hipLaunchKernelGGL(batch_decide_kernel, dim3(nd), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a, iters,
+                       last ? 1 : 0);
+    return hipGetLastError();
+}
 
 int batch_type(int k, int gk, int lb)
 {

@@ -1222,6 +1222,12 @@ struct omt_bctx {
     int nblocks;
     std::vector<BatchPair> pairs;
     std::vector<BatchPairState> st;
+    struct Graph {
+        hipGraphExec_t exec;
+        int K, par0, w0;
+    } graphs[2];
+    int ngraphs;
+    unsigned *host_stopped;  // pinned
 };
 
 namespace {
@@ -1281,9 +1287,105 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
 
 void destroy_batch(omt_bctx *h)
 {
+    for (int q = 0; q < h->ngraphs; ++q) (void)hipGraphExecDestroy(h->graphs[q].exec);
+    if (h->host_stopped) (void)hipHostFree(h->host_stopped);
     for (omt_ctx *c : h->ctx) omt_destroy(c);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
+}
+
+
+// Persistent schedule: the whole solve in one launch with grid barriers,
+// captured in a graph together with the clearing of its state.
+omt_status batch_solve_persistent(omt_bctx *h, const BatchArgs &ba)
+{
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_zero(h->d_state, sizeof(BatchPairState) * h->B, h->cap);
+    if (e == hipSuccess) e = launch_zero(h->d_bar, sizeof(unsigned) * BAR_WORDS, h->cap);
+    if (e == hipSuccess) e = launch_batch(ba, h->comp, h->nblocks, h->cap);
+    hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(OMT_EDEVICE, "capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiateWithFlags(&exec, graph, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, h->cap);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->cap);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(OMT_EDEVICE, "batched solve: %s", hipGetErrorString(e));
+    return OMT_OK;
+}
+
+// Enqueue one check interval of nblk iterations: nblk launches that advance
+// every unfinished problem, then the metrics and the decisions.
+hipError_t batch_enqueue_interval(omt_bctx *h, const BatchArgs &ba, int64_t nblk, int par0, int w0, bool last,
+                                  hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    int var = 0;
+    for (int64_t i = 0; i < nblk && e == hipSuccess; ++i) {
+        var = int((par0 + i) & 1) * 4 + w0 * 2 + (i == nblk - 1 ? 1 : 0);
+        e = launch_batch_step(ba, h->comp, var, s);
+    }
+    if (e == hipSuccess) e = launch_batch_check(ba, h->comp, var, int(nblk), last, s);
+    return e;
+}
+
+// Graph schedule: every full check interval is replayed as one captured
+// graph; after each interval only the count of stopped problems is read.
+omt_status batch_solve_graphs(omt_bctx *h, const BatchArgs &ba, int64_t max_iters, int K)
+{
+    HIP_TRY(launch_zero(h->d_state, sizeof(BatchPairState) * h->B, h->cap));
+    HIP_TRY(launch_zero(h->d_bar, sizeof(unsigned) * BAR_WORDS, h->cap));
+    int64_t done = 0;
+    int nchecks = 0;
+    unsigned stopped = 0;
+    while (done < max_iters && stopped < unsigned(h->B)) {
+        const int64_t nblk = std::min<int64_t>(K, max_iters - done);
+        const bool last = done + nblk == max_iters;
+        const int par0 = int(done & 1), w0 = nchecks & 1;
+        if (nblk == K && !last) {
+            omt_bctx::Graph *g = nullptr;
+            for (int q = 0; q < h->ngraphs; ++q)
+                if (h->graphs[q].K == K && h->graphs[q].par0 == par0 && h->graphs[q].w0 == w0) g = &h->graphs[q];
+            if (!g) {
+                if (h->ngraphs == 2) {
+                    (void)hipGraphExecDestroy(h->graphs[0].exec);
+                    h->graphs[0] = h->graphs[1];
+                    h->ngraphs = 1;
+                }
+                hipGraph_t graph = nullptr;
+                HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+                hipError_t e = batch_enqueue_interval(h, ba, K, par0, w0, false, h->cap);
+                hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return fail(OMT_EDEVICE, "capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+                }
+                omt_bctx::Graph ng;
+                ng.K = K;
+                ng.par0 = par0;
+                ng.w0 = w0;
+                e = hipGraphInstantiateWithFlags(&ng.exec, graph, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) return fail(OMT_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+                h->graphs[h->ngraphs++] = ng;
+                g = &h->graphs[h->ngraphs - 1];
+            }
+            HIP_TRY(hipGraphLaunch(g->exec, h->cap));
+        } else {
+            HIP_TRY(batch_enqueue_interval(h, ba, nblk, par0, w0, last, h->cap));
+        }
+        done += nblk;
+        ++nchecks;
+        HIP_TRY(hipMemcpyAsync(h->host_stopped, h->d_bar + 3, sizeof(unsigned), hipMemcpyDeviceToHost, h->cap));
+        HIP_TRY(hipStreamSynchronize(h->cap));
+        stopped = *h->host_stopped;
+    }
+    return OMT_OK;
 }
 
 }  // namespace
@@ -1370,6 +1472,7 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         e = hipMemcpyAsync(h->d_mtile_pair, mtp.data(), sizeof(int) * mtp.size(), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&h->host_stopped), sizeof(unsigned), 0);
     int bpc = 0, cus = 0, dev = 0;
     if (e == hipSuccess) e = batch_blocks_per_cu(comp, &bpc);
     if (e == hipSuccess) e = hipGetDevice(&dev);
@@ -1429,25 +1532,13 @@ omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, in
     ba.check_every = K;
     ba.max_iters = max_iters;
     ba.tol = tol;
-    // the whole solve is one graph: clear the barrier and states, then the
-    // persistent kernel
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_zero(h->d_state, sizeof(BatchPairState) * h->B, h->cap);
-    if (e == hipSuccess) e = launch_zero(h->d_bar, sizeof(unsigned) * BAR_WORDS, h->cap);
-    if (e == hipSuccess) e = launch_batch(ba, h->comp, h->nblocks, h->cap);
-    hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return fail(OMT_EDEVICE, "capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    if (std::getenv("OMT_BATCH_PERSISTENT")) {
+        omt_status ps = batch_solve_persistent(h, ba);
+        if (ps != OMT_OK) return ps;
+    } else {
+        omt_status gs = batch_solve_graphs(h, ba, max_iters, K);
+        if (gs != OMT_OK) return gs;
     }
-    e = hipGraphInstantiateWithFlags(&exec, graph, 0);
-    if (e == hipSuccess) e = hipGraphLaunch(exec, h->cap);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->cap);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(OMT_EDEVICE, "batched solve: %s", hipGetErrorString(e));
     unsigned bar[4];
     HIP_TRY(hipMemcpy(bar, h->d_bar, sizeof(bar), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(h->st.data(), h->d_state, sizeof(BatchPairState) * h->B, hipMemcpyDeviceToHost));

@@ -114,6 +114,11 @@ constexpr int BAR_WORDS = BAR_GROUP0 + BAR_STRIDE * BAR_GROUPS;
 int batch_type(int k, int gk, int lb);  // -1 if not compiled into the batched kernel
 hipError_t batch_blocks_per_cu(bool comp, int *blocks);
 hipError_t launch_batch(const BatchArgs &a, bool comp, int nblocks, hipStream_t s);
+// one iteration of every unfinished problem; var = par * 4 + wcur * 2 + check
+hipError_t launch_batch_step(const BatchArgs &a, bool comp, int var, hipStream_t s);
+// metrics tiles and per-problem decisions after a check iteration (iters =
+// iterations since the previous check; last = the solve ends here)
+hipError_t launch_batch_check(const BatchArgs &a, bool comp, int var, int iters, bool last, hipStream_t s);
 
 // ---------------------------------------------------------------- auxiliary
 

@@ -36,12 +36,15 @@ def _plain(torch, pr, iters, tol):
     return s, info
 
 
+@pytest.mark.parametrize("persistent", [False, True])
 @pytest.mark.parametrize("comp", [False, True])
-def test_batch_fixed_iterations_bit_identical(comp):
+def test_batch_fixed_iterations_bit_identical(comp, persistent, monkeypatch):
     torch = cuda()
     from paper_1712_10279_amd import omt
+    if persistent:
+        monkeypatch.setenv("OMT_BATCH_PERSISTENT", "1")
     probs = _problems(torch, 40, comp)
-    note(f"case: batch of {len(probs)} fixed 300 iterations comp={comp}")
+    note(f"case: batch of {len(probs)} fixed 300 iterations comp={comp} persistent={persistent}")
     b = omt.BatchSolver(probs)
     infos = b.solve(300, 0.0, 64)
     Vb = b.distance()
@@ -55,11 +58,14 @@ def test_batch_fixed_iterations_bit_identical(comp):
         assert Vb[q] == s.distance()[0]
 
 
-def test_batch_to_tolerance_same_decisions():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_to_tolerance_same_decisions(persistent, monkeypatch):
     torch = cuda()
     from paper_1712_10279_amd import omt
+    if persistent:
+        monkeypatch.setenv("OMT_BATCH_PERSISTENT", "1")
     probs = _problems(torch, 50, True)
-    note("case: batch to tol 1e-3")
+    note(f"case: batch to tol 1e-3 persistent={persistent}")
     b = omt.BatchSolver(probs)
     infos = b.solve(200000, 1e-3, 64)
     for q, pr in enumerate(probs):
