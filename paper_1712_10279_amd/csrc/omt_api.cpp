@@ -1225,6 +1225,7 @@ struct omt_bctx {
     struct Graph {
         hipGraphExec_t exec;
         int K, par0, w0;
+        double tol;  // baked into the decision launches
     } graphs[2];
     int ngraphs;
     unsigned *host_stopped;  // pinned
@@ -1350,7 +1351,9 @@ omt_status batch_solve_graphs(omt_bctx *h, const BatchArgs &ba, int64_t max_iter
         if (nblk == K && !last) {
             omt_bctx::Graph *g = nullptr;
             for (int q = 0; q < h->ngraphs; ++q)
-                if (h->graphs[q].K == K && h->graphs[q].par0 == par0 && h->graphs[q].w0 == w0) g = &h->graphs[q];
+                if (h->graphs[q].K == K && h->graphs[q].par0 == par0 && h->graphs[q].w0 == w0 &&
+                    h->graphs[q].tol == ba.tol)
+                    g = &h->graphs[q];
             if (!g) {
                 if (h->ngraphs == 2) {
                     (void)hipGraphExecDestroy(h->graphs[0].exec);
@@ -1369,6 +1372,7 @@ omt_status batch_solve_graphs(omt_bctx *h, const BatchArgs &ba, int64_t max_iter
                 ng.K = K;
                 ng.par0 = par0;
                 ng.w0 = w0;
+                ng.tol = ba.tol;
                 e = hipGraphInstantiateWithFlags(&ng.exec, graph, 0);
                 (void)hipGraphDestroy(graph);
                 if (e != hipSuccess) return fail(OMT_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
