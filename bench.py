@@ -44,6 +44,10 @@ def _parse():
     ap.add_argument("--pairs", type=int, default=96, help="batched workload: number of pairs")
     ap.add_argument("--tol", type=float, default=0.0, help="time-to-tolerance workloads: tolerance (0: workload's)")
     ap.add_argument("--cap", type=int, default=3_000_000, help="time-to-tolerance workloads: iteration cap")
+    ap.add_argument("--leg", default="both", choices=["both", "plain", "batched"],
+                    help="batched workload: time both legs (ratio) or one of them")
+    ap.add_argument("--precision", default="auto", choices=["auto", "f32comp", "f64"],
+                    help="time-to-tolerance workloads: iterate precision (auto: the workload's)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device-to-device copies of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -107,48 +111,87 @@ def _line(metric, value, unit, steps, warmup, ms, config, dtype="f32", **extra):
     return d
 
 
+def _precision(a, default):
+    """(torch dtype, compensated flag, label) of a time-to-tolerance run."""
+    import torch
+    p = default if a.precision == "auto" else a.precision
+    if p == "f64":
+        return torch.float64, False, "FP64"
+    return torch.float32, True, "compensated FP32"
+
+
+def _dtype_name(dt):
+    import torch
+    return "f64" if dt == torch.float64 else "f32"
+
+
 def bench_batched(a):
     """96 pairs (sides 64..512, k in {1, 3}) to a relative residual of 1e-5:
-    the persistent batched kernel against the per-pair solves, same tau, K,
-    tol and compensated FP32 potential (identical iteration counts)."""
+    the batched solve against the per-pair solves, same tau, K, tol and
+    precision (identical iteration counts).  FP64 by default: FP32 iterates,
+    even with the compensated potential, stall above 1e-5 on some pairs."""
     import torch
     from paper_1712_10279_amd import inputs as I
     from paper_1712_10279_amd import omt
     tol = a.tol or 1e-5
+    dt, comp, label = _precision(a, "f64")
     specs = I.batch_spec(a.pairs)
     probs = []
     for sp in specs:
         d = I.batch_pair(sp)
-        probs.append(dict(rho0=torch.as_tensor(d["rho0"], dtype=torch.float32, device="cuda"),
-                          rho1=torch.as_tensor(d["rho1"], dtype=torch.float32, device="cuda"),
+        probs.append(dict(rho0=torch.as_tensor(d["rho0"], dtype=dt, device="cuda"),
+                          rho1=torch.as_tensor(d["rho1"], dtype=dt, device="cuda"),
                           edges=d["edges"], alpha=d["alpha"], tau=I.tuned_tau(sp["side"], sp["side"]),
-                          compensated=True))
-    # plain: one solve after another on one stream
-    solvers = [omt.Solver(p["rho0"], p["rho1"], p["edges"], alpha=p["alpha"], tau=p["tau"], compensated=True)
-               for p in probs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain = [s.solve(a.cap, tol, 64) for s in solvers]
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    del solvers
-    b = omt.BatchSolver(probs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch = b.solve(a.cap, tol, 64)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    its = [i["iters"] for i in batch]
-    same = all(p["iters"] == q["iters"] for p, q in zip(plain, batch))
+                          compensated=comp))
+    print(f"# batched: {len(probs)} pairs, {label}, tol {tol}", file=sys.stderr, flush=True)
+    plain = batch = None
+    t_plain = t_batch = None
+    if a.leg in ("both", "plain"):
+        # plain: one solve after another on one stream
+        solvers = [omt.Solver(p["rho0"], p["rho1"], p["edges"], alpha=p["alpha"], tau=p["tau"], compensated=comp)
+                   for p in probs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain = []
+        for q, s in enumerate(solvers):
+            plain.append(s.solve(a.cap, tol, 64))
+            sp = specs[q]
+            print(f"# plain {q}: side {sp['side']} k {sp['k']} {plain[-1]['iters']} it "
+                  f"(residual {plain[-1]['residual']:.2e}), {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        del solvers
+    if a.leg in ("both", "batched"):
+        os.environ["OMT_VERBOSE"] = "1"
+        b = omt.BatchSolver(probs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch = b.solve(a.cap, tol, 64)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        print(f"# batched: {t_batch:.1f} s", file=sys.stderr, flush=True)
+    ref = batch if batch is not None else plain
+    its = [i["iters"] for i in ref]
     cells = sum(sp["side"] ** 2 * i for sp, i in zip(specs, its))
-    return _line("time to 1e-5 relative residual, batched vs plain", t_plain / t_batch, "x", sum(its), 0,
-                 t_batch * 1e3 / max(its), {"workload": f"batched_{a.pairs}_pairs_side64-512_k1or3",
-                                            "pairs": a.pairs, "tol": tol, "check_every": 64,
-                                            "potential": "compensated FP32", "parallelism": "single-gpu"},
-                 batched_s=t_batch, plain_s=t_plain, converged=sum(i["converged"] for i in batch),
-                 same_iterations=same, iterations={"min": min(its), "median": sorted(its)[len(its) // 2],
-                                                   "max": max(its), "total": sum(its)},
-                 batched_cell_iter_per_s=cells / t_batch, plain_cell_iter_per_s=cells / t_plain)
+    extra = dict(converged=sum(i["converged"] for i in ref),
+                 iterations={"min": min(its), "median": sorted(its)[len(its) // 2], "max": max(its),
+                             "total": sum(its)}, per_pair_iterations=its)
+    if plain is not None:
+        extra.update(plain_s=t_plain, plain_cell_iter_per_s=cells / t_plain)
+    if batch is not None:
+        extra.update(batched_s=t_batch, batched_cell_iter_per_s=cells / t_batch)
+    if plain is not None and batch is not None:
+        extra["same_iterations"] = all(p["iters"] == q["iters"] for p, q in zip(plain, batch))
+        value, unit, metric = t_plain / t_batch, "x", "time to 1e-5 relative residual, batched vs plain"
+    else:
+        value, unit = (t_plain if batch is None else t_batch), "s"
+        metric = f"time to 1e-5 relative residual, {a.leg} leg"
+    return _line(metric, value, unit, sum(its), 0, value * 1e3 / max(its) if unit == "s" else t_batch * 1e3 / max(its),
+                 dtype=_dtype_name(dt),
+                 config={"workload": f"batched_{a.pairs}_pairs_side64-512_k1or3", "pairs": a.pairs, "tol": tol,
+                         "check_every": 64, "precision": label, "leg": a.leg, "parallelism": "single-gpu"},
+                 **extra)
 
 
 def bench_rgb(a):
@@ -157,25 +200,28 @@ def bench_rgb(a):
     from paper_1712_10279_amd import inputs as I
     from paper_1712_10279_amd import omt
     tol = a.tol or 1e-5
+    dt, comp, label = _precision(a, "f32comp")
     out = []
     total_t, total_it = 0.0, 0
     for alpha in (0.5, 1.0, 4.0):
         d = I.rgb_256(alpha)
-        s = omt.Solver(torch.as_tensor(d["rho0"], dtype=torch.float32, device="cuda"),
-                       torch.as_tensor(d["rho1"], dtype=torch.float32, device="cuda"), d["edges"], alpha=alpha,
-                       tau=I.tuned_tau(256, 256), compensated=True)
+        s = omt.Solver(torch.as_tensor(d["rho0"], dtype=dt, device="cuda"),
+                       torch.as_tensor(d["rho1"], dtype=dt, device="cuda"), d["edges"], alpha=alpha,
+                       tau=I.tuned_tau(256, 256), compensated=comp)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = s.solve(a.cap, tol, 64)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        total_t += dt
+        el = time.perf_counter() - t0
+        total_t += el
         total_it += info["iters"]
-        out.append({"alpha": alpha, "seconds": dt, "iterations": info["iters"], "converged": info["converged"],
+        print(f"# rgb alpha {alpha}: {info['iters']} it, {el:.2f} s", file=sys.stderr, flush=True)
+        out.append({"alpha": alpha, "seconds": el, "iterations": info["iters"], "converged": info["converged"],
                     "V": s.distance()[0], "rel_gap": info["rel_gap"]})
     return _line("time to 1e-5 relative residual", total_t, "s", total_it, 0, total_t * 1e3 / total_it,
-                 {"workload": "vomt_256x256_k3_triangle_3alphas", "tol": tol, "potential": "compensated FP32",
-                  "tau": I.tuned_tau(256, 256), "parallelism": "single-gpu"}, pairs=out)
+                 dtype=_dtype_name(dt), config={"workload": "vomt_256x256_k3_triangle_3alphas", "tol": tol,
+                                                "precision": label, "tau": I.tuned_tau(256, 256),
+                                                "parallelism": "single-gpu"}, pairs=out)
 
 
 def bench_loss(a):
@@ -184,18 +230,19 @@ def bench_loss(a):
     from paper_1712_10279_amd import inputs as I
     from paper_1712_10279_amd import omt
     tol = a.tol or 1e-6
+    dt, comp, label = _precision(a, "f64")
     ds = [I.loss_512(q) for q in range(8)]
-    r0 = torch.stack([torch.as_tensor(d["rho0"], dtype=torch.float32, device="cuda") for d in ds]).requires_grad_(True)
-    r1 = torch.stack([torch.as_tensor(d["rho1"], dtype=torch.float32, device="cuda") for d in ds])
+    r0 = torch.stack([torch.as_tensor(d["rho0"], dtype=dt, device="cuda") for d in ds]).requires_grad_(True)
+    r1 = torch.stack([torch.as_tensor(d["rho1"], dtype=dt, device="cuda") for d in ds])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    V = omt.omt_loss(r0, r1, I.TRIANGLE, max_iters=a.cap, tol=tol, tau=I.tuned_tau(512, 512), compensated=True)
+    V = omt.omt_loss(r0, r1, I.TRIANGLE, max_iters=a.cap, tol=tol, tau=I.tuned_tau(512, 512), compensated=comp)
     V.sum().backward()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return _line("forward+backward time, 8 pairs to 1e-6", dt, "s", 8, 0, dt * 1e3 / 8,
-                 {"workload": "loss_8x512x512_k3_triangle", "tol": tol, "potential": "compensated FP32",
-                  "parallelism": "single-gpu"}, V=[float(v) for v in V.detach().cpu()])
+    el = time.perf_counter() - t0
+    return _line("forward+backward time, 8 pairs to 1e-6", el, "s", 8, 0, el * 1e3 / 8, dtype=_dtype_name(dt),
+                 config={"workload": "loss_8x512x512_k3_triangle", "tol": tol, "precision": label,
+                         "parallelism": "single-gpu"}, V=[float(v) for v in V.detach().cpu()])
 
 
 def main():

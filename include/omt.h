@@ -173,13 +173,21 @@ omt_status omt_destroy(omt_handle h);
  * graphs solved together: every iteration advances all unfinished pairs in
  * one launch, and the launches of a check interval are replayed as one HIP
  * graph.  params[b], rho0[b], rho1[b] as for omt_create (device pointers);
- * one workspace of omt_batch_workspace_bytes(). */
+ * one workspace of omt_batch_workspace_bytes().  Compiled problem types:
+ * k = 1 without edges, k = 2 with one edge, k = 3 on the triangle or on the
+ * path; anything else is OMT_EUNSUPPORTED.  Every problem of a batch shares
+ * the dtype and OMT_FLAG_COMPENSATED_PHI (else OMT_EINVAL); each problem's
+ * iterates are bit-identical to those of its own omt_solve. */
 omt_status omt_batch_workspace_bytes(int32_t B, const omt_params *params, size_t *bytes);
 omt_status omt_batch_create(int32_t B, const omt_params *params, const void *const *rho0,
                             const void *const *rho1, void *workspace, size_t ws_bytes, void *stream,
                             omt_batch_handle *out);
 /* Each pair stops at its own first check with residual <= tol (checks every
- * check_every iterations, as omt_solve); infos: host array of B (nullable). */
+ * check_every iterations, as omt_solve); infos: host array of B (nullable).
+ * Every call starts all B problems from their current iterates.  Environment:
+ * OMT_BATCH_PERSISTENT selects the single persistent launch with grid
+ * barriers instead of graph-replayed per-iteration launches; OMT_VERBOSE
+ * prints a line to stderr whenever more problems have stopped. */
 omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, int32_t check_every,
                            omt_info *infos);
 omt_status omt_batch_distance(omt_batch_handle h, double *V /* host, B */);

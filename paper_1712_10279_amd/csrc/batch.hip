@@ -15,8 +15,9 @@
 // wave sees the abort flag and leaves, and the host reports the error.
 //
 // Supported problem types (compiled in): k = 1 without edges, k = 2 with one
-// edge, k = 3 on the complete graph (triangle) or on the path; FP32 with or
-// without the compensated potential; one iteration per pass.
+// edge, k = 3 on the complete graph (triangle) or on the path; FP32 (with or
+// without the compensated potential) or FP64, one dtype per batch; one
+// iteration per pass.
 
 #include "metrics_device.h"
 
@@ -77,34 +78,34 @@ __device__ bool grid_sync(unsigned *bar, unsigned nblocks)
     return s_abort != 0;
 }
 
-template <bool COMP>
-__device__ __forceinline__ void strip_by_type(int type, const StepArgs<float> &a, int wc, int wr, int lane)
+template <typename R, bool COMP>
+__device__ __forceinline__ void strip_by_type(int type, const StepArgs<R> &a, int wc, int wr, int lane)
 {
     switch (type) {
-        case 0: process_strip<float, 1, G_NONE, 0, 1, COMP>(a, wc, wr, lane); break;
-        case 1: process_strip<float, 2, G_PATH, 1, 1, COMP>(a, wc, wr, lane); break;
-        case 2: process_strip<float, 3, G_COMPLETE, 3, 1, COMP>(a, wc, wr, lane); break;
-        case 3: process_strip<float, 3, G_PATH, 2, 1, COMP>(a, wc, wr, lane); break;
+        case 0: process_strip<R, 1, G_NONE, 0, 1, COMP>(a, wc, wr, lane); break;
+        case 1: process_strip<R, 2, G_PATH, 1, 1, COMP>(a, wc, wr, lane); break;
+        case 2: process_strip<R, 3, G_COMPLETE, 3, 1, COMP>(a, wc, wr, lane); break;
+        case 3: process_strip<R, 3, G_PATH, 2, 1, COMP>(a, wc, wr, lane); break;
         default: break;
     }
 }
 
-template <bool COMP>
-__device__ __forceinline__ void metrics_by_type(int type, const StepArgs<float> &a, int wc, int wr, int lane,
+template <typename R, bool COMP>
+__device__ __forceinline__ void metrics_by_type(int type, const StepArgs<R> &a, int wc, int wr, int lane,
                                                 double (&v)[NMET])
 {
     switch (type) {
-        case 0: tile_metrics<float, 1, G_NONE, 0, COMP>(a, wc, wr, lane, v); break;
-        case 1: tile_metrics<float, 2, G_PATH, 1, COMP>(a, wc, wr, lane, v); break;
-        case 2: tile_metrics<float, 3, G_COMPLETE, 3, COMP>(a, wc, wr, lane, v); break;
-        case 3: tile_metrics<float, 3, G_PATH, 2, COMP>(a, wc, wr, lane, v); break;
+        case 0: tile_metrics<R, 1, G_NONE, 0, COMP>(a, wc, wr, lane, v); break;
+        case 1: tile_metrics<R, 2, G_PATH, 1, COMP>(a, wc, wr, lane, v); break;
+        case 2: tile_metrics<R, 3, G_COMPLETE, 3, COMP>(a, wc, wr, lane, v); break;
+        case 3: tile_metrics<R, 3, G_PATH, 2, COMP>(a, wc, wr, lane, v); break;
         default:
             for (int q = 0; q < NMET; ++q) v[q] = 0.0;
             break;
     }
 }
 
-template <bool COMP>
+template <typename R, bool COMP>
 __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_kernel(const BatchArgs ba)
 {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_kernel(const Ba
             if (__hip_atomic_load(&ba.state[p].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
             const BatchPair &bp = ba.pairs[p];
             const int local = t - bp.tile0;
-            strip_by_type<COMP>(bp.type, bp.v[var], local % bp.ncolw, local / bp.ncolw, lane);
+            strip_by_type<R, COMP>(bp.type, bp.template args<R>(var), local % bp.ncolw, local / bp.ncolw, lane);
         }
         if (grid_sync(ba.bar, nblocks)) return;
         if (!check) continue;
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_kernel(const Ba
             const BatchPair &bp = ba.pairs[p];
             const int local = t - bp.mtile0;
             double v[NMET];
-            metrics_by_type<COMP>(bp.type, bp.v[var], local % bp.mcolw, local / bp.mcolw, lane, v);
+            metrics_by_type<R, COMP>(bp.type, bp.template args<R>(var), local % bp.mcolw, local / bp.mcolw, lane, v);
 #pragma unroll
             for (int q = 0; q < NMET; ++q) {
                 const double s = wave_sum(v[q]);
@@ -153,9 +154,9 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_kernel(const Ba
             reduce_tiles(ba.partials, bp.mtile0, bp.mtiles, lane, st.met);
             if (lane == 0) {
                 const double *m = st.met;
-                const double R = m[0] / bp.mu + (bp.l > 0 ? m[1] / bp.nu : 0.0) + m[2] / bp.tau - 2.0 * m[3];
-                const bool conv = ba.tol > 0.0 && R <= ba.tol * ba.tol * bp.R0;
-                const bool bad = !isfinite(R) || !isfinite(m[4]);
+                const double Rk = m[0] / bp.mu + (bp.l > 0 ? m[1] / bp.nu : 0.0) + m[2] / bp.tau - 2.0 * m[3];
+                const bool conv = ba.tol > 0.0 && Rk <= ba.tol * ba.tol * bp.R0;
+                const bool bad = !isfinite(Rk) || !isfinite(m[4]);
                 st.iters = it + 1;
                 st.checks = nchecks + 1;
                 st.cur = 1 - par;
@@ -192,7 +193,7 @@ __device__ __forceinline__ int remap_block(int b, int nwg)
     return (x < r) ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
 }
 
-template <bool COMP>
+template <typename R, bool COMP>
 __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_step_kernel(const BatchArgs ba, int var)
 {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -202,10 +203,10 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_step_kernel(con
     if (ba.state[p].done) return;
     const BatchPair &bp = ba.pairs[p];
     const int local = t - bp.tile0;
-    strip_by_type<COMP>(bp.type, bp.v[var], local % bp.ncolw, local / bp.ncolw, lane);
+    strip_by_type<R, COMP>(bp.type, bp.template args<R>(var), local % bp.ncolw, local / bp.ncolw, lane);
 }
 
-template <bool COMP>
+template <typename R, bool COMP>
 __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_metrics_kernel(const BatchArgs ba, int var)
 {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_metrics_kernel(
     const BatchPair &bp = ba.pairs[p];
     const int local = t - bp.mtile0;
     double v[NMET];
-    metrics_by_type<COMP>(bp.type, bp.v[var], local % bp.mcolw, local / bp.mcolw, lane, v);
+    metrics_by_type<R, COMP>(bp.type, bp.template args<R>(var), local % bp.mcolw, local / bp.mcolw, lane, v);
 #pragma unroll
     for (int q = 0; q < NMET; ++q) {
         const double s = wave_sum(v[q]);
@@ -255,28 +256,31 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_decide_kernel(c
 
 }  // namespace
 
-hipError_t launch_batch_step(const BatchArgs &a, bool comp, int var, hipStream_t s)
+hipError_t launch_batch_step(const BatchArgs &a, int dtype, bool comp, int var, hipStream_t s)
 {
-    const int nb = (a.total_tiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG;
-    if (comp)
-        hipLaunchKernelGGL(batch_step_kernel<true>, dim3(nb), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a, var);
+    const dim3 grid((a.total_tiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG), block(WAVE * STEP_WAVES_PER_WG);
+    if (dtype == 1)
+        hipLaunchKernelGGL((batch_step_kernel<double, false>), grid, block, 0, s, a, var);
+    else if (comp)
+        hipLaunchKernelGGL((batch_step_kernel<float, true>), grid, block, 0, s, a, var);
     else
-        hipLaunchKernelGGL(batch_step_kernel<false>, dim3(nb), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a, var);
+        hipLaunchKernelGGL((batch_step_kernel<float, false>), grid, block, 0, s, a, var);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_check(const BatchArgs &a, bool comp, int var, int iters, bool last, hipStream_t s)
+hipError_t launch_batch_check(const BatchArgs &a, int dtype, bool comp, int var, int iters, bool last, hipStream_t s)
 {
-    const int nb = (a.total_mtiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG;
-    if (comp)
-        hipLaunchKernelGGL(batch_metrics_kernel<true>, dim3(nb), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a, var);
+    const dim3 grid((a.total_mtiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG), block(WAVE * STEP_WAVES_PER_WG);
+    if (dtype == 1)
+        hipLaunchKernelGGL((batch_metrics_kernel<double, false>), grid, block, 0, s, a, var);
+    else if (comp)
+        hipLaunchKernelGGL((batch_metrics_kernel<float, true>), grid, block, 0, s, a, var);
     else
-        hipLaunchKernelGGL(batch_metrics_kernel<false>, dim3(nb), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a, var);
+        hipLaunchKernelGGL((batch_metrics_kernel<float, false>), grid, block, 0, s, a, var);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nd = (a.B + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG;
-    hipLaunchKernelGGL(batch_decide_kernel, dim3(nd), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a, iters,
-                       last ? 1 : 0);
+    hipLaunchKernelGGL(batch_decide_kernel, dim3(nd), block, 0, s, a, iters, last ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -289,19 +293,23 @@ int batch_type(int k, int gk, int lb)
     return -1;
 }
 
-hipError_t batch_blocks_per_cu(bool comp, int *blocks)
+hipError_t batch_blocks_per_cu(int dtype, bool comp, int *blocks)
 {
-    if (comp)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, batch_kernel<true>, WAVE * STEP_WAVES_PER_WG, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, batch_kernel<false>, WAVE * STEP_WAVES_PER_WG, 0);
+    const int bs = WAVE * STEP_WAVES_PER_WG;
+    if (dtype == 1) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, batch_kernel<double, false>, bs, 0);
+    if (comp) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, batch_kernel<float, true>, bs, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, batch_kernel<float, false>, bs, 0);
 }
 
-hipError_t launch_batch(const BatchArgs &a, bool comp, int nblocks, hipStream_t s)
+hipError_t launch_batch(const BatchArgs &a, int dtype, bool comp, int nblocks, hipStream_t s)
 {
-    if (comp)
-        hipLaunchKernelGGL(batch_kernel<true>, dim3(nblocks), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a);
+    const dim3 block(WAVE * STEP_WAVES_PER_WG);
+    if (dtype == 1)
+        hipLaunchKernelGGL((batch_kernel<double, false>), dim3(nblocks), block, 0, s, a);
+    else if (comp)
+        hipLaunchKernelGGL((batch_kernel<float, true>), dim3(nblocks), block, 0, s, a);
     else
-        hipLaunchKernelGGL(batch_kernel<false>, dim3(nblocks), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a);
+        hipLaunchKernelGGL((batch_kernel<float, false>), dim3(nblocks), block, 0, s, a);
     return hipGetLastError();
 }
 

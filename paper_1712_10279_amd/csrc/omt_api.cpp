@@ -1219,6 +1219,7 @@ struct omt_bctx {
     unsigned *d_bar;
     int total_tiles, total_mtiles;
     bool comp;
+    int dtype;
     int nblocks;
     std::vector<BatchPair> pairs;
     std::vector<BatchPairState> st;
@@ -1242,7 +1243,7 @@ struct BatchLayout {
     int total_tiles, total_mtiles;
 };
 
-omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, bool *comp)
+omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, bool *comp, int *dtype)
 {
     if (B < 1) return fail(OMT_EINVAL, "batch size %d < 1", B);
     if (!params) return fail(OMT_EINVAL, "params is NULL");
@@ -1252,7 +1253,8 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
         Resolved r;
         omt_status s = resolve(&params[p], r);
         if (s != OMT_OK) return fail(s, "problem %d: %s", p, g_last_error.c_str());
-        if (r.dtype != OMT_F32) return fail(OMT_EUNSUPPORTED, "problem %d: the batched kernel runs FP32 only", p);
+        if (p == 0) *dtype = r.dtype;
+        if (r.dtype != *dtype) return fail(OMT_EINVAL, "problem %d: all problems of a batch must share the dtype", p);
         if (batch_type(r.k, r.gk, r.lb) < 0)
             return fail(OMT_EUNSUPPORTED, "problem %d: k = %d with this graph is not compiled into the batched kernel",
                         p, r.k);
@@ -1305,7 +1307,7 @@ omt_status batch_solve_persistent(omt_bctx *h, const BatchArgs &ba)
     HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = launch_zero(h->d_state, sizeof(BatchPairState) * h->B, h->cap);
     if (e == hipSuccess) e = launch_zero(h->d_bar, sizeof(unsigned) * BAR_WORDS, h->cap);
-    if (e == hipSuccess) e = launch_batch(ba, h->comp, h->nblocks, h->cap);
+    if (e == hipSuccess) e = launch_batch(ba, h->dtype, h->comp, h->nblocks, h->cap);
     hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -1329,9 +1331,9 @@ hipError_t batch_enqueue_interval(omt_bctx *h, const BatchArgs &ba, int64_t nblk
     int var = 0;
     for (int64_t i = 0; i < nblk && e == hipSuccess; ++i) {
         var = int((par0 + i) & 1) * 4 + w0 * 2 + (i == nblk - 1 ? 1 : 0);
-        e = launch_batch_step(ba, h->comp, var, s);
+        e = launch_batch_step(ba, h->dtype, h->comp, var, s);
     }
-    if (e == hipSuccess) e = launch_batch_check(ba, h->comp, var, int(nblk), last, s);
+    if (e == hipSuccess) e = launch_batch_check(ba, h->dtype, h->comp, var, int(nblk), last, s);
     return e;
 }
 
@@ -1344,6 +1346,7 @@ omt_status batch_solve_graphs(omt_bctx *h, const BatchArgs &ba, int64_t max_iter
     int64_t done = 0;
     int nchecks = 0;
     unsigned stopped = 0;
+    const bool verbose = std::getenv("OMT_VERBOSE") != nullptr;
     while (done < max_iters && stopped < unsigned(h->B)) {
         const int64_t nblk = std::min<int64_t>(K, max_iters - done);
         const bool last = done + nblk == max_iters;
@@ -1387,6 +1390,9 @@ omt_status batch_solve_graphs(omt_bctx *h, const BatchArgs &ba, int64_t max_iter
         ++nchecks;
         HIP_TRY(hipMemcpyAsync(h->host_stopped, h->d_bar + 3, sizeof(unsigned), hipMemcpyDeviceToHost, h->cap));
         HIP_TRY(hipStreamSynchronize(h->cap));
+        if (verbose && *h->host_stopped != stopped)
+            std::fprintf(stderr, "omt batch: %u of %d problems stopped after %lld iterations\n", *h->host_stopped,
+                         h->B, (long long)done);
         stopped = *h->host_stopped;
     }
     return OMT_OK;
@@ -1401,7 +1407,8 @@ omt_status omt_batch_workspace_bytes(int32_t B, const omt_params *params, size_t
     if (!bytes) return fail(OMT_EINVAL, "bytes is NULL");
     BatchLayout L;
     bool comp = false;
-    omt_status s = batch_layout(B, params, L, &comp);
+    int dtype = 0;
+    omt_status s = batch_layout(B, params, L, &comp, &dtype);
     if (s != OMT_OK) return s;
     *bytes = L.total;
     return OMT_OK;
@@ -1417,7 +1424,8 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         return fail(OMT_EINVAL, "workspace missing or not 256-byte aligned");
     BatchLayout L;
     bool comp = false;
-    omt_status s = batch_layout(B, params, L, &comp);
+    int dtype = 0;
+    omt_status s = batch_layout(B, params, L, &comp, &dtype);
     if (s != OMT_OK) return s;
     if (ws_bytes < L.total) return fail(OMT_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
 
@@ -1426,6 +1434,7 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
     h->stream = static_cast<hipStream_t>(stream);
     h->ws = static_cast<char *>(workspace);
     h->comp = comp;
+    h->dtype = dtype;
     h->total_tiles = L.total_tiles;
     h->total_mtiles = L.total_mtiles;
     h->d_pairs = reinterpret_cast<BatchPair *>(h->ws + L.off_pairs);
@@ -1478,7 +1487,7 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&h->host_stopped), sizeof(unsigned), 0);
     int bpc = 0, cus = 0, dev = 0;
-    if (e == hipSuccess) e = batch_blocks_per_cu(comp, &bpc);
+    if (e == hipSuccess) e = batch_blocks_per_cu(dtype, comp, &bpc);
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) {
@@ -1518,7 +1527,10 @@ omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, in
         for (int var = 0; var < 8; ++var) {
             const int par = var / 4, wv = (var / 2) % 2, chk = var % 2;
             const int ci = (c->cur + par) & 1, wi = (c->wcur + wv) & 1;
-            fill_args(bp.v[var], c, ci, 1 - ci, wi, chk ? 1 - wi : wi, rows, ncolw, nroww, 0);
+            if (h->dtype == OMT_F64)
+                fill_args(bp.args_mut<double>(var), c, ci, 1 - ci, wi, chk ? 1 - wi : wi, rows, ncolw, nroww, 0);
+            else
+                fill_args(bp.args_mut<float>(var), c, ci, 1 - ci, wi, chk ? 1 - wi : wi, rows, ncolw, nroww, 0);
         }
     }
     HIP_TRY(hipStreamSynchronize(h->stream));

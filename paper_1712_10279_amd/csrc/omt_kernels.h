@@ -83,7 +83,18 @@ hipError_t launch_reduce_tiles(const double *partials, int ntiles, double *out, 
 // arguments for the iteration parity par (potential / flux buffers), the
 // current w buffer and whether the iteration is a check (w out of place).
 struct BatchPair {
-    StepArgs<float> v[8];
+    // step arguments of the batch's dtype (StepArgs<float> or <double>)
+    alignas(16) unsigned char v[8][sizeof(StepArgs<double>)];
+    template <typename R>
+    __host__ __device__ const StepArgs<R> &args(int var) const
+    {
+        return *reinterpret_cast<const StepArgs<R> *>(v[var]);
+    }
+    template <typename R>
+    StepArgs<R> &args_mut(int var)
+    {
+        return *reinterpret_cast<StepArgs<R> *>(v[var]);
+    }
     int type, l;
     int ncolw, tile0, ntiles;   // step strips: across, first in the list, count
     int mcolw, mtile0, mtiles;  // metric tiles likewise
@@ -112,13 +123,15 @@ constexpr int BAR_GROUPS = 8, BAR_GROUP0 = 32, BAR_STRIDE = 32;
 constexpr int BAR_WORDS = BAR_GROUP0 + BAR_STRIDE * BAR_GROUPS;
 
 int batch_type(int k, int gk, int lb);  // -1 if not compiled into the batched kernel
-hipError_t batch_blocks_per_cu(bool comp, int *blocks);
-hipError_t launch_batch(const BatchArgs &a, bool comp, int nblocks, hipStream_t s);
+// dtype: 0 FP32 (comp: compensated potential), 1 FP64
+hipError_t batch_blocks_per_cu(int dtype, bool comp, int *blocks);
+hipError_t launch_batch(const BatchArgs &a, int dtype, bool comp, int nblocks, hipStream_t s);
 // one iteration of every unfinished problem; var = par * 4 + wcur * 2 + check
-hipError_t launch_batch_step(const BatchArgs &a, bool comp, int var, hipStream_t s);
+hipError_t launch_batch_step(const BatchArgs &a, int dtype, bool comp, int var, hipStream_t s);
 // metrics tiles and per-problem decisions after a check iteration (iters =
 // iterations since the previous check; last = the solve ends here)
-hipError_t launch_batch_check(const BatchArgs &a, bool comp, int var, int iters, bool last, hipStream_t s);
+hipError_t launch_batch_check(const BatchArgs &a, int dtype, bool comp, int var, int iters, bool last,
+                              hipStream_t s);
 
 // ---------------------------------------------------------------- auxiliary
 

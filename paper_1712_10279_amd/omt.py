@@ -312,8 +312,8 @@ def omt_loss(rho0, rho1, edges=None, max_iters=100000, tol=1e-6, check_every=64,
 class BatchSolver:
     """Many problems solved together by the persistent batched kernel
     (omt_batch_create ... omt_batch_destroy).  ``problems`` is a list of
-    dicts with keys rho0, rho1 (GPU tensors, float32), edges and any Config
-    field (alpha, tau, compensated, ...)."""
+    dicts with keys rho0, rho1 (GPU tensors, all float32 or all float64),
+    edges and any Config field (alpha, tau, compensated, ...)."""
 
     def __init__(self, problems):
         torch = _torch()
@@ -324,15 +324,18 @@ class BatchSolver:
         r0 = (C.c_void_p * self.B)()
         r1 = (C.c_void_p * self.B)()
         dev = None
+        self.dtype = problems[0]["rho0"].dtype if problems else torch.float32
         for b, pr in enumerate(problems):
             a0, a1 = pr["rho0"].contiguous(), pr["rho1"].contiguous()
-            if a0.dtype != torch.float32 or not a0.is_cuda:
-                raise ValueError("batched problems must be float32 GPU tensors")
+            if a0.dtype not in (torch.float32, torch.float64) or not a0.is_cuda:
+                raise ValueError("batched problems must be float32 or float64 GPU tensors")
+            if a0.dtype != self.dtype or a1.dtype != self.dtype:
+                raise ValueError("every problem of a batch must have the same dtype")
             dev = a0.device
             m, n, k = (int(x) for x in a0.shape)
             edges = np.zeros((0, 2), np.int32) if pr.get("edges") is None else pr["edges"]
             kw = {key: v for key, v in pr.items() if key not in ("rho0", "rho1", "edges")}
-            p, keep = make_params(m, n, k, edges, Config(**kw), F32)
+            p, keep = make_params(m, n, k, edges, Config(**kw), F64 if self.dtype == torch.float64 else F32)
             ps[b] = p
             self._keep += [keep, a0, a1]
             r0[b], r1[b] = a0.data_ptr(), a1.data_ptr()
@@ -366,7 +369,7 @@ class BatchSolver:
 
     def grad(self):
         torch = _torch()
-        d0 = [torch.empty(s[:3], dtype=torch.float32, device=self.device) for s in self.shapes]
+        d0 = [torch.empty(s[:3], dtype=self.dtype, device=self.device) for s in self.shapes]
         d1 = [torch.empty_like(x) for x in d0]
         p0 = (C.c_void_p * self.B)(*[x.data_ptr() for x in d0])
         p1 = (C.c_void_p * self.B)(*[x.data_ptr() for x in d1])
@@ -376,9 +379,9 @@ class BatchSolver:
     def get_state(self, b):
         torch = _torch()
         m, n, k, l = self.shapes[b]
-        phi = torch.empty((m, n, k), dtype=torch.float32, device=self.device)
-        u = torch.empty((m, n, k, 2), dtype=torch.float32, device=self.device)
-        w = torch.zeros((m, n, max(l, 1)), dtype=torch.float32, device=self.device)
+        phi = torch.empty((m, n, k), dtype=self.dtype, device=self.device)
+        u = torch.empty((m, n, k, 2), dtype=self.dtype, device=self.device)
+        w = torch.zeros((m, n, max(l, 1)), dtype=self.dtype, device=self.device)
         _check(lib().omt_batch_get_state(self._h, int(b), _ptr(phi), _ptr(u), _ptr(w) if l else C.c_void_p(0)),
                "omt_batch_get_state")
         return {"phi": phi, "u": u, "w": w[:, :, :l]}

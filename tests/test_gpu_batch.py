@@ -19,11 +19,12 @@ SHAPES = [  # (m, n, k, edges)
 ]
 
 
-def _problems(torch, seed, comp=False, tau=None):
+def _problems(torch, seed, comp=False, tau=None, dtype=None):
+    dtype = dtype or torch.float32
     out = []
     for q, (m, n, k, e) in enumerate(SHAPES):
         r0, r1 = I.random_pair(seed + q, m, n, k)
-        out.append(dict(rho0=to_dev(torch, r0, torch.float32), rho1=to_dev(torch, r1, torch.float32), edges=e,
+        out.append(dict(rho0=to_dev(torch, r0, dtype), rho1=to_dev(torch, r1, dtype), edges=e,
                         alpha=0.5 + 0.3 * q, tau=tau or I.default_tau(m, n), compensated=comp))
     return out
 
@@ -37,14 +38,15 @@ def _plain(torch, pr, iters, tol):
 
 
 @pytest.mark.parametrize("persistent", [False, True])
-@pytest.mark.parametrize("comp", [False, True])
-def test_batch_fixed_iterations_bit_identical(comp, persistent, monkeypatch):
+@pytest.mark.parametrize("mode", ["f32", "f32comp", "f64"])
+def test_batch_fixed_iterations_bit_identical(mode, persistent, monkeypatch):
     torch = cuda()
     from paper_1712_10279_amd import omt
     if persistent:
         monkeypatch.setenv("OMT_BATCH_PERSISTENT", "1")
-    probs = _problems(torch, 40, comp)
-    note(f"case: batch of {len(probs)} fixed 300 iterations comp={comp} persistent={persistent}")
+    comp = mode == "f32comp"
+    probs = _problems(torch, 40, comp, dtype=torch.float64 if mode == "f64" else torch.float32)
+    note(f"case: batch of {len(probs)} fixed 300 iterations mode={mode} persistent={persistent}")
     b = omt.BatchSolver(probs)
     infos = b.solve(300, 0.0, 64)
     Vb = b.distance()
@@ -93,3 +95,38 @@ def test_batch_rejects_unsupported_problem():
         omt.BatchSolver([dict(rho0=to_dev(torch, r0, torch.float32), rho1=to_dev(torch, r1, torch.float32),
                               edges=I.path_edges(5))])
     assert e.value.status == omt.EUNSUPPORTED
+
+
+def test_batch_f64_to_tolerance_matches_oracle():
+    """FP64 batch to a tight tolerance: the same decisions as each problem's
+    own solve, and the distance of the oracle run for the same count."""
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    import oracle
+    probs = _problems(torch, 70, dtype=torch.float64)[:3]
+    note("case: FP64 batch of 3 to tol 1e-6")
+    b = omt.BatchSolver(probs)
+    infos = b.solve(20000, 1e-6, 64)
+    Vb = b.distance()
+    for q, pr in enumerate(probs):
+        s, info = _plain(torch, pr, 20000, 1e-6)
+        assert infos[q]["iters"] == info["iters"] and infos[q]["converged"] == info["converged"]
+        gs, bs = s.get_state(), b.get_state(q)
+        for key in ("phi", "u", "w"):
+            assert torch.equal(gs[key], bs[key]), (q, key)
+        m, n, k, e = SHAPES[q]
+        r0 = pr["rho0"].cpu().numpy()
+        r1 = pr["rho1"].cpu().numpy()
+        res = oracle.solve_pair(r0, r1, e if e is not None else np.zeros((0, 2)), alpha=pr["alpha"],
+                                tau=pr["tau"], max_iters=infos[q]["iters"])
+        note(f"  problem {q}: {infos[q]['iters']} it, V batch {Vb[q]:.12g} oracle {res['primal']:.12g}")
+        assert abs(Vb[q] - res["primal"]) <= 1e-9 * max(1.0, abs(res["primal"]))
+
+
+def test_batch_rejects_mixed_dtypes():
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    probs = _problems(torch, 80)[:2]
+    probs[1] = dict(probs[1], rho0=probs[1]["rho0"].double(), rho1=probs[1]["rho1"].double())
+    with pytest.raises(ValueError):
+        omt.BatchSolver(probs)
