@@ -9,7 +9,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "omt_oracle.c")
+SRCS = [os.path.join(HERE, "omt_oracle.c"), os.path.join(HERE, "momt_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
@@ -17,7 +17,7 @@ def build(verbose: bool = False) -> str:
     # -ffp-contract=off keeps every expression exactly as written (no fused
     # multiply-adds), so the oracle's rounding is that of the plain formula.
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-Wall", "-Wextra", "-o", LIB + ".tmp", *SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

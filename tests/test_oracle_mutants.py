@@ -40,3 +40,41 @@ def test_pins_reject_mutant(tmp_path, name, old, new):
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant '{name}' survived the pins:\n{r.stdout[-2000:]}"
+
+
+MSRC = os.path.join(ROOT, "oracle", "momt_oracle.c")
+
+MATRIX_MUTANTS = [
+    ("commutator order in grad_L", "Z[s * k * k + q] = LX[q] - XL[q];", "Z[s * k * k + q] = XL[q] - LX[q];"),
+    ("missing conjugate in the inner product", "s += creal(X[q] * conj(Y[q]));", "s += creal(X[q] * Y[q]);"),
+    ("dropped W extrapolation", "Wk->bw[q] = 2.0 * w1[q] - w[q];", "Wk->bw[q] = w1[q];"),
+    ("nuclear shrink loses the sign", "g[p] = r > 0.0 ? (ev[p] > 0.0 ? r : -r) : 0.0;", "g[p] = r > 0.0 ? r : 0.0;"),
+    ("skew shrink mapped back with +i", "for (int q = 0; q < kk; ++q) Xs[q] = -I * G[q];",
+     "for (int q = 0; q < kk; ++q) Xs[q] = I * G[q];"),
+    ("nu without the factor 4", "p->nu = lm > 0.0 ? 1.0 / (4.0 * p->tau * lm) : 0.0;",
+     "p->nu = lm > 0.0 ? 1.0 / (2.0 * p->tau * lm) : 0.0;"),
+    ("trace mean kept in f", "for (int a = 0; a < k; ++a) f[q * kk + a * k + a] -= mean;",
+     "for (int a = 0; a < k; ++a) f[q * kk + a * k + a] -= 0.0 * mean;"),
+    ("sign in the real image of a Hermitian matrix", "S[a * n + (k + b)] = -B;", "S[a * n + (k + b)] = B;"),
+    ("mu rule of S-OMT", "if (p->mu <= 0.0) p->mu = p->h * p->h / (32.0 * p->tau);",
+     "if (p->mu <= 0.0) p->mu = p->h * p->h / (16.0 * p->tau);"),
+    ("W threshold without alpha", "morc_shrink_block(p->wnorm, 0, k, l, (double *)b, p->alpha * p->nu);",
+     "morc_shrink_block(p->wnorm, 0, k, l, (double *)b, p->nu);"),
+]
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+@pytest.mark.parametrize("name,old,new", MATRIX_MUTANTS, ids=[m[0] for m in MATRIX_MUTANTS])
+def test_matrix_pins_reject_mutant(tmp_path, name, old, new):
+    src = open(MSRC).read()
+    assert old in src, f"pattern for '{name}' not found"
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new, 1))
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-o", str(so), SRC, str(mut),
+                    "-lm"], check=True)
+    env = dict(os.environ, OMT_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_moracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant '{name}' survived the pins:\n{r.stdout[-2000:]}"
