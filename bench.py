@@ -46,6 +46,9 @@ def _parse():
     ap.add_argument("--cap", type=int, default=3_000_000, help="time-to-tolerance workloads: iteration cap")
     ap.add_argument("--leg", default="both", choices=["both", "plain", "batched"],
                     help="batched workload: time both legs (ratio) or one of them")
+    ap.add_argument("--plain-range", default="", metavar="A:B",
+                    help="batched workload, plain leg: solve only pairs A..B-1 (the per-pair solves are independent, "
+                         "so the leg can be timed in parts)")
     ap.add_argument("--precision", default="auto", choices=["auto", "f32comp", "f64"],
                     help="time-to-tolerance workloads: iterate precision (auto: the workload's)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -148,12 +151,13 @@ def bench_batched(a):
     t_plain = t_batch = None
     if a.leg in ("both", "plain"):
         # plain: one solve after another on one stream
+        lo, hi = (int(x) for x in a.plain_range.split(":")) if a.plain_range else (0, len(probs))
         solvers = [omt.Solver(p["rho0"], p["rho1"], p["edges"], alpha=p["alpha"], tau=p["tau"], compensated=comp)
-                   for p in probs]
+                   for p in probs[lo:hi]]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plain = []
-        for q, s in enumerate(solvers):
+        for q, s in enumerate(solvers, start=lo):
             plain.append(s.solve(a.cap, tol, 64))
             sp = specs[q]
             print(f"# plain {q}: side {sp['side']} k {sp['k']} {plain[-1]['iters']} it "
@@ -173,6 +177,8 @@ def bench_batched(a):
         print(f"# batched: {t_batch:.1f} s", file=sys.stderr, flush=True)
     ref = batch if batch is not None else plain
     its = [i["iters"] for i in ref]
+    if batch is None and a.plain_range:
+        specs = specs[lo:hi]
     cells = sum(sp["side"] ** 2 * i for sp, i in zip(specs, its))
     extra = dict(converged=sum(i["converged"] for i in ref),
                  iterations={"min": min(its), "median": sorted(its)[len(its) // 2], "max": max(its),
@@ -190,7 +196,8 @@ def bench_batched(a):
     return _line(metric, value, unit, sum(its), 0, value * 1e3 / max(its) if unit == "s" else t_batch * 1e3 / max(its),
                  dtype=_dtype_name(dt),
                  config={"workload": f"batched_{a.pairs}_pairs_side64-512_k1or3", "pairs": a.pairs, "tol": tol,
-                         "check_every": 64, "precision": label, "leg": a.leg, "parallelism": "single-gpu"},
+                         "check_every": 64, "precision": label, "leg": a.leg,
+                         "plain_range": a.plain_range or None, "parallelism": "single-gpu"},
                  **extra)
 
 

@@ -196,6 +196,62 @@ __global__ void xfer_kernel(XferArgs a)
     }
 }
 
+__device__ __forceinline__ int matrix_ncoord(int k, int real, int herm)
+{
+    return real ? (herm ? k * (k + 1) / 2 : k * (k - 1) / 2) : k * k;
+}
+
+__global__ void matrix_xfer_kernel(MatrixXferArgs a)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // (pixel, matrix)
+    if (q >= a.npix * a.count) return;
+    const int k = a.k, nc = matrix_ncoord(k, a.real, a.herm);
+    const int ent = a.real ? 1 : 2;                  // values per matrix entry
+    const int64_t mbase = q * k * k * ent;           // first entry of this matrix
+    const int64_t cbase = q * nc;                    // first coordinate of this group
+    const double r2 = 1.4142135623730951, ir2 = 0.70710678118654752;
+    auto cidx = [&](int c) { return (cbase + c) * a.cstride + a.coff; };
+    auto midx = [&](int r, int c) { return mbase + (int64_t(r) * k + c) * ent; };
+    // diagonal
+    const int nd = (a.herm || !a.real) ? k : 0;
+    for (int d = 0; d < nd; ++d) {
+        if (a.pack) {
+            const double v = a.herm ? ldv(a.src, a.dtype, midx(d, d)) : ldv(a.src, a.dtype, midx(d, d) + 1);
+            stv(a.dst, a.dtype, cidx(d), v);
+        } else {
+            const double v = ldv(a.src, a.dtype, cidx(d));
+            if (a.real) {
+                stv(a.dst, a.dtype, midx(d, d), v);
+            } else {
+                stv(a.dst, a.dtype, midx(d, d), a.herm ? v : 0.0);
+                stv(a.dst, a.dtype, midx(d, d) + 1, a.herm ? 0.0 : v);
+            }
+        }
+    }
+    if (!a.pack && a.real && !a.herm)
+        for (int d = 0; d < k; ++d) stv(a.dst, a.dtype, midx(d, d), 0.0);
+    // pairs a < b
+    int c = nd;
+    for (int r = 0; r < k; ++r)
+        for (int s = r + 1; s < k; ++s) {
+            if (a.pack) {
+                stv(a.dst, a.dtype, cidx(c), r2 * ldv(a.src, a.dtype, midx(r, s)));
+                if (!a.real) stv(a.dst, a.dtype, cidx(c + 1), r2 * ldv(a.src, a.dtype, midx(r, s) + 1));
+            } else {
+                const double re = ir2 * ldv(a.src, a.dtype, cidx(c));
+                const double im = a.real ? 0.0 : ir2 * ldv(a.src, a.dtype, cidx(c + 1));
+                // X_rs = re + i im; X_sr = conj (Hermitian) or -conj (skew)
+                stv(a.dst, a.dtype, midx(r, s), re);
+                stv(a.dst, a.dtype, midx(s, r), a.herm ? re : -re);
+                if (!a.real) {
+                    stv(a.dst, a.dtype, midx(r, s) + 1, im);
+                    stv(a.dst, a.dtype, midx(s, r) + 1, a.herm ? -im : im);
+                }
+            }
+            c += a.real ? 1 : 2;
+        }
+}
+
 __global__ void zero_kernel(uint32_t *p, int64_t n)
 {
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
@@ -239,6 +295,14 @@ hipError_t launch_xfer(const XferArgs &a, hipStream_t s)
 {
     const int64_t n = (int64_t)a.m * a.n;
     hipLaunchKernelGGL(xfer_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_matrix_xfer(const MatrixXferArgs &a, hipStream_t s)
+{
+    const int64_t n = a.npix * a.count;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(matrix_xfer_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -78,9 +78,13 @@ __device__ bool grid_sync(unsigned *bar, unsigned nblocks)
     return s_abort != 0;
 }
 
+// The step arguments are copied out of the table once, before any store, so
+// that the compiler need not reload them after every store it cannot prove
+// disjoint from the table.
 template <typename R, bool COMP>
-__device__ __forceinline__ void strip_by_type(int type, const StepArgs<R> &a, int wc, int wr, int lane)
+__device__ __forceinline__ void strip_by_type(int type, const StepArgs<R> &src, int wc, int wr, int lane)
 {
+    const StepArgs<R> a = src;
     switch (type) {
         case 0: process_strip<R, 1, G_NONE, 0, 1, COMP>(a, wc, wr, lane); break;
         case 1: process_strip<R, 2, G_PATH, 1, 1, COMP>(a, wc, wr, lane); break;
@@ -91,9 +95,10 @@ __device__ __forceinline__ void strip_by_type(int type, const StepArgs<R> &a, in
 }
 
 template <typename R, bool COMP>
-__device__ __forceinline__ void metrics_by_type(int type, const StepArgs<R> &a, int wc, int wr, int lane,
+__device__ __forceinline__ void metrics_by_type(int type, const StepArgs<R> &src, int wc, int wr, int lane,
                                                 double (&v)[NMET])
 {
+    const StepArgs<R> a = src;
     switch (type) {
         case 0: tile_metrics<R, 1, G_NONE, 0, COMP>(a, wc, wr, lane, v); break;
         case 1: tile_metrics<R, 2, G_PATH, 1, COMP>(a, wc, wr, lane, v); break;

@@ -22,6 +22,22 @@ namespace dev {
 
 constexpr int MET_ROWS = 16;
 
+// sum_g wt_g ||x_g||_2 of a grouped entry-wise norm (see group_scales)
+template <int N, typename W>
+__device__ __forceinline__ double group_norm(const W *wt, const double (&x)[N])
+{
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        if (wt[c] > W(0)) {
+            const bool pair = (c + 1 < N) && wt[c + 1] == W(0);
+            const double r = pair ? sqrt(x[c] * x[c] + x[c + 1] * x[c + 1]) : fabs(x[c]);
+            s += double(wt[c]) * r;
+        }
+    }
+    return s;
+}
+
 template <typename R, int K, int GK, int L, bool COMP>
 __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int wr, int lane, double (&v)[NMET])
 {
@@ -41,26 +57,27 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
             const bool on = L > 0 && e < a.l;
-            we0[e] = on ? double(w0[e * P + o]) : 0.0;
-            we1[e] = on ? double(w1[e * P + o]) : 0.0;
+            we0[e] = on ? double(ld_field(&w0[e * P + o])) : 0.0;
+            we1[e] = on ? double(ld_field(&w1[e * P + o])) : 0.0;
         }
         double u2 = 0.0, sq = 0.0;
+        double gx[K], gy[K];  // u' of this pixel (grouped norm of the matrix kinds)
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-            double p0 = double(phi0[c * P + o]), p1 = double(phi1[c * P + o]);
+            double p0 = double(ld_field(&phi0[c * P + o])), p1 = double(ld_field(&phi1[c * P + o]));
             if (COMP) {
-                p0 += double(a.plo_in[c * P + o]);
-                p1 += double(a.plo_out[c * P + o]);
+                p0 += double(ld_field(&a.plo_in[c * P + o]));
+                p1 += double(ld_field(&a.plo_out[c * P + o]));
             }
             const double dp = p1 - p0;
-            const double ux0 = i < a.m - 1 ? double(u0[c * P + o]) : 0.0;
-            const double ux1 = i < a.m - 1 ? double(u1[c * P + o]) : 0.0;
-            const double uy0 = j < a.n - 1 ? double(u0[(K + c) * P + o]) : 0.0;
-            const double uy1 = j < a.n - 1 ? double(u1[(K + c) * P + o]) : 0.0;
-            const double xl0 = i > 0 ? double(u0[c * P + oi]) : 0.0;
-            const double xl1 = i > 0 ? double(u1[c * P + oi]) : 0.0;
-            const double yl0 = j > 0 ? double(u0[(K + c) * P + oj]) : 0.0;
-            const double yl1 = j > 0 ? double(u1[(K + c) * P + oj]) : 0.0;
+            const double ux0 = i < a.m - 1 ? double(ld_field(&u0[c * P + o])) : 0.0;
+            const double ux1 = i < a.m - 1 ? double(ld_field(&u1[c * P + o])) : 0.0;
+            const double uy0 = j < a.n - 1 ? double(ld_field(&u0[(K + c) * P + o])) : 0.0;
+            const double uy1 = j < a.n - 1 ? double(ld_field(&u1[(K + c) * P + o])) : 0.0;
+            const double xl0 = i > 0 ? double(ld_field(&u0[c * P + oi])) : 0.0;
+            const double xl1 = i > 0 ? double(ld_field(&u1[c * P + oi])) : 0.0;
+            const double yl0 = j > 0 ? double(ld_field(&u0[(K + c) * P + oj])) : 0.0;
+            const double yl1 = j > 0 ? double(ld_field(&u1[(K + c) * P + oj])) : 0.0;
             const double dux = ux1 - ux0, duy = uy1 - uy0;
             const double ddiv = ((dux - (xl1 - xl0)) + duy - (yl1 - yl0)) * inv_h;
             const double div1 = ((ux1 - xl1) + uy1 - yl1) * inv_h;
@@ -69,7 +86,7 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             if constexpr (L > 0) {
 #pragma unroll
                 for (int e = 0; e < LA; ++e) {
-                    if constexpr (GK == G_DENSE) {
+                    if constexpr (GK == G_DENSE || GK == G_MATRIX) {
                         dgd += double(a.gm[c * LMAX + e]) * (we1[e] - we0[e]);
                         dg1 += double(a.gm[c * LMAX + e]) * we1[e];
                     } else {
@@ -84,7 +101,7 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
                     }
                 }
             }
-            const double fc = double(a.f[c * P + o]);
+            const double fc = double(ld_field(&a.f[c * P + o]));
             v[0] += dux * dux + duy * duy;
             v[2] += dp * dp;
             v[3] += dp * (ddiv - dgd);
@@ -93,6 +110,8 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             v[6] += r * r;
             v[7] += p1;
             sq += ux1 * ux1 + uy1 * uy1;
+            gx[c] = ux1;
+            gy[c] = uy1;
             if (a.unorm == 0)
                 v[4] += sqrt(ux1 * ux1 + uy1 * uy1);
             else if (a.unorm == 1)
@@ -101,6 +120,9 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
                 u2 += ux1 * ux1 + uy1 * uy1;
         }
         if (a.unorm == 2) v[4] += sqrt(u2);
+        if constexpr (GK == G_MATRIX) {
+            if (a.unorm == 3) v[4] += group_norm<K>(a.uwt, gx) + group_norm<K>(a.uwt, gy);
+        }
         double wn = 0.0, w2 = 0.0;
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
@@ -108,7 +130,10 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             wn += fabs(we1[e]);
             w2 += we1[e] * we1[e];
         }
-        v[4] += a.alpha * (a.wnorm == 0 ? wn : sqrt(w2));
+        if (GK == G_MATRIX && a.wnorm == 2)
+            v[4] += a.alpha * group_norm<LA>(a.wwt, we1);
+        else
+            v[4] += a.alpha * (a.wnorm == 0 ? wn : sqrt(w2));
         if (a.eps > 0.0) v[4] += a.eps * (sq + w2);  // quadratic regularisation
     }
 }

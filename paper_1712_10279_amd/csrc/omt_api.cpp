@@ -17,7 +17,10 @@
 #include <vector>
 
 #include "../../include/omt.h"
+#include "../../include/omt_matrix.h"
 #include "omt_kernels.h"
+
+#include <complex>
 
 namespace omt {
 
@@ -144,8 +147,8 @@ omt_status fail(omt_status s, const char *fmt, ...)
 
 // ------------------------------------------------------------------ graph
 
-// Largest eigenvalue of a symmetric matrix by the cyclic Jacobi method.
-double jacobi_lambda_max(std::vector<double> A, int k)
+// Eigenvalues of a symmetric matrix by the cyclic Jacobi method.
+std::vector<double> jacobi_eigenvalues(std::vector<double> A, int k)
 {
     for (int sweep = 0; sweep < 64; ++sweep) {
         double off = 0.0, tot = 0.0;
@@ -174,8 +177,15 @@ double jacobi_lambda_max(std::vector<double> A, int k)
                 }
             }
     }
+    std::vector<double> ev(k);
+    for (int p = 0; p < k; ++p) ev[p] = A[p * k + p];
+    return ev;
+}
+
+double jacobi_lambda_max(std::vector<double> A, int k)
+{
     double mx = 0.0;
-    for (int p = 0; p < k; ++p) mx = std::max(mx, A[p * k + p]);
+    for (double v : jacobi_eigenvalues(std::move(A), k)) mx = std::max(mx, v);
     return mx;
 }
 
@@ -187,8 +197,12 @@ struct Resolved {
     int unorm, wnorm, dtype;
     bool comp;
     int tblock, rows;
-    std::vector<int> cls;  // mass class per channel
+    std::vector<int> cls;  // mass class per channel (-1: no mass constraint, no mean removed)
     int ncls;
+    // matrix method (G_MATRIX): dense operator, row c / column e at
+    // gmat[c * LMAX + e], and the group weights of the grouped norms
+    bool matrix = false;
+    std::vector<double> gmat, uwt, wwt;
 };
 
 omt_status resolve(const omt_params *p, Resolved &r)
@@ -433,6 +447,14 @@ void fill_args(StepArgs<R> &a, const omt_ctx *h, int ci, int co, int wi, int wo,
     a.wreg = R(1.0 / (1.0 + 2.0 * r.nu * r.eps));
     for (int q = 0; q < KMAX * LMAX; ++q) a.gm[q] = R(0);
     for (int q = 0; q < LMAX; ++q) a.ic[q] = R(0);
+    for (int q = 0; q < KMAX; ++q) a.uwt[q] = R(1);
+    for (int q = 0; q < LMAX; ++q) a.wwt[q] = R(1);
+    if (r.matrix) {
+        for (int q = 0; q < KMAX * LMAX; ++q) a.gm[q] = R(r.gmat[q]);
+        for (int c = 0; c < r.k; ++c) a.uwt[c] = R(r.uwt[c]);
+        for (int e = 0; e < r.l; ++e) a.wwt[e] = R(r.wwt[e]);
+        return;
+    }
     for (int e = 0; e < r.l; ++e) {
         a.ic[e] = R(1.0 / r.cost[e]);
         a.gm[r.edges[2 * e] * LMAX + e] = R(1.0 / r.cost[e]);
@@ -731,6 +753,9 @@ omt_status graph_interval(omt_ctx *h, int K, int T, int rowsT, int rows1)
     return read_results(h, NMET, h->cap);
 }
 
+omt_status create_resolved(const Resolved &r, const void *rho0, const void *rho1, void *workspace, size_t ws_bytes,
+                           void *stream, omt_handle *out);
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -778,6 +803,19 @@ omt_status omt_create(const omt_params *p, const void *rho0, const void *rho1, v
     Resolved r;
     omt_status s = resolve(p, r);
     if (s != OMT_OK) return s;
+    return create_resolved(r, rho0, rho1, workspace, ws_bytes, stream, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The set-up of omt_create for an already resolved problem (also used by the
+// matrix method, whose data arrive packed into coordinates).
+omt_status create_resolved(const Resolved &r, const void *rho0, const void *rho1, void *workspace, size_t ws_bytes,
+                           void *stream, omt_handle *out)
+{
+    omt_status s = OMT_OK;
     if (!rho0 || !rho1) return fail(OMT_EINVAL, "rho0 / rho1 is NULL");
     if (!workspace) return fail(OMT_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(OMT_EINVAL, "workspace not 256-byte aligned");
@@ -833,6 +871,7 @@ omt_status omt_create(const omt_params *p, const void *rho0, const void *rho1, v
     std::vector<double> s0(r.ncls, 0.0), s1(r.ncls, 0.0), a0(r.ncls, 0.0), a1(r.ncls, 0.0), cnt(r.ncls, 0.0);
     for (int c = 0; c < r.k; ++c) {
         const int g = r.cls[c];
+        if (g < 0) continue;
         s0[g] += sums[4 * c];
         s1[g] += sums[4 * c + 1];
         a0[g] += sums[4 * c + 2];
@@ -846,7 +885,7 @@ omt_status omt_create(const omt_params *p, const void *rho0, const void *rho1, v
             return bail(fail(OMT_EMASS, "mass class %d: sum rho0 = %.9g, sum rho1 = %.9g (relative %.3g > 1e-6)", g,
                              s0[g], s1[g], rel));
     }
-    for (int c = 0; c < r.k; ++c) h->host[c] = (s1[r.cls[c]] - s0[r.cls[c]]) / cnt[r.cls[c]];
+    for (int c = 0; c < r.k; ++c) h->host[c] = r.cls[c] < 0 ? 0.0 : (s1[r.cls[c]] - s0[r.cls[c]]) / cnt[r.cls[c]];
     e = hipMemcpyAsync(h->vec, h->host, sizeof(double) * r.k, hipMemcpyHostToDevice, h->stream);
     // f = rho1 - rho0 - class mean, state = 0
     MakeFArgs fa;
@@ -872,6 +911,10 @@ omt_status omt_create(const omt_params *p, const void *rho0, const void *rho1, v
     *out = h;
     return OMT_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 omt_status omt_solve(omt_handle h, int64_t max_iters, double tol, int32_t check_every, omt_info *info)
 {
@@ -961,10 +1004,11 @@ omt_status omt_grad(omt_handle h, void *d_rho0, void *d_rho1)
     if (s != OMT_OK) return s;
     std::vector<double> cs(r.ncls, 0.0), cn(r.ncls, 0.0);
     for (int c = 0; c < r.k; ++c) {
+        if (r.cls[c] < 0) continue;
         cs[r.cls[c]] += h->host[c];
         cn[r.cls[c]] += double(r.m) * r.n;
     }
-    for (int c = 0; c < r.k; ++c) h->host[c] = cs[r.cls[c]] / cn[r.cls[c]];
+    for (int c = 0; c < r.k; ++c) h->host[c] = r.cls[c] < 0 ? 0.0 : cs[r.cls[c]] / cn[r.cls[c]];
     HIP_TRY(hipMemcpyAsync(h->vec, h->host, sizeof(double) * r.k, hipMemcpyHostToDevice, h->stream));
     XferArgs xa;
     xa.src = h->phi[h->cur];
@@ -1217,7 +1261,8 @@ struct omt_bctx {
     int *d_tile_pair, *d_mtile_pair;
     double *d_partials;
     unsigned *d_bar;
-    int total_tiles, total_mtiles;
+    int total_tiles, total_mtiles;  // strips / metric tiles in the current lists
+    int full_tiles, full_mtiles;    // ... with every problem in them
     bool comp;
     int dtype;
     int nblocks;
@@ -1234,7 +1279,10 @@ struct omt_bctx {
 
 namespace {
 
-constexpr int BATCH_ROWS_DEFAULT = 8;
+// Rows per strip in the batched kernel: a strip's rows are a chain of
+// dependent steps, so small grids take short strips (their iterations are
+// latency-bound) and large grids 8 rows (fewer halo rows per strip).
+int batch_rows_default(int m) { return std::max(2, std::min(8, (m + 31) / 32)); }
 
 struct BatchLayout {
     std::vector<size_t> off, bytes;
@@ -1264,7 +1312,7 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
         L.off.push_back(o);
         L.bytes.push_back(b);
         o += align256(b);
-        const int rows = r.rows > 0 ? r.rows : BATCH_ROWS_DEFAULT;
+        const int rows = r.rows > 0 ? r.rows : batch_rows_default(r.m);
         const int ncolw = (r.n + WAVE - 1) / WAVE;
         L.rows.push_back(rows);
         L.ntiles.push_back(ncolw * ((r.m + rows - 1) / rows));
@@ -1339,7 +1387,40 @@ hipError_t batch_enqueue_interval(omt_bctx *h, const BatchArgs &ba, int64_t nblk
 
 // Graph schedule: every full check interval is replayed as one captured
 // graph; after each interval only the count of stopped problems is read.
-omt_status batch_solve_graphs(omt_bctx *h, const BatchArgs &ba, int64_t max_iters, int K)
+// Strip and metric-tile lists of the problems marked active, in problem
+// order; each problem's first strip / tile index is stored in its
+// descriptor.  Uploaded on the capture stream; the descriptors are uploaded
+// by the caller.
+hipError_t batch_set_lists(omt_bctx *h, const std::vector<char> &active)
+{
+    std::vector<int> tp, mtp;
+    for (int p = 0; p < h->B; ++p) {
+        BatchPair &bp = h->pairs[p];
+        if (!active[p]) continue;
+        bp.tile0 = int(tp.size());
+        bp.mtile0 = int(mtp.size());
+        for (int q = 0; q < bp.ntiles; ++q) tp.push_back(p);
+        for (int q = 0; q < bp.mtiles; ++q) mtp.push_back(p);
+    }
+    h->total_tiles = int(tp.size());
+    h->total_mtiles = int(mtp.size());
+    hipError_t e = hipSuccess;
+    if (!tp.empty())
+        e = hipMemcpyAsync(h->d_tile_pair, tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, h->cap);
+    if (e == hipSuccess && !mtp.empty())
+        e = hipMemcpyAsync(h->d_mtile_pair, mtp.data(), sizeof(int) * mtp.size(), hipMemcpyHostToDevice, h->cap);
+    // the host vectors go out of scope: finish the copies first
+    if (e == hipSuccess) e = hipStreamSynchronize(h->cap);
+    return e;
+}
+
+void batch_drop_graphs(omt_bctx *h)
+{
+    for (int q = 0; q < h->ngraphs; ++q) (void)hipGraphExecDestroy(h->graphs[q].exec);
+    h->ngraphs = 0;
+}
+
+omt_status batch_solve_graphs(omt_bctx *h, BatchArgs ba, int64_t max_iters, int K)
 {
     HIP_TRY(launch_zero(h->d_state, sizeof(BatchPairState) * h->B, h->cap));
     HIP_TRY(launch_zero(h->d_bar, sizeof(unsigned) * BAR_WORDS, h->cap));
@@ -1393,7 +1474,31 @@ omt_status batch_solve_graphs(omt_bctx *h, const BatchArgs &ba, int64_t max_iter
         if (verbose && *h->host_stopped != stopped)
             std::fprintf(stderr, "omt batch: %u of %d problems stopped after %lld iterations\n", *h->host_stopped,
                          h->B, (long long)done);
+        const bool more = *h->host_stopped != stopped;
         stopped = *h->host_stopped;
+        if (more && stopped < unsigned(h->B) && done < max_iters) {
+            // drop the stopped problems from the lists once their strips are
+            // a quarter of the launch: later launches then cover only the
+            // problems still running (new graphs are captured for them)
+            HIP_TRY(hipMemcpyAsync(h->st.data(), h->d_state, sizeof(BatchPairState) * h->B, hipMemcpyDeviceToHost,
+                                   h->cap));
+            HIP_TRY(hipStreamSynchronize(h->cap));
+            std::vector<char> active(h->B, 0);
+            int live = 0;
+            for (int p = 0; p < h->B; ++p) {
+                active[p] = h->st[p].done ? 0 : 1;
+                if (active[p]) live += h->pairs[p].ntiles;
+            }
+            if (4 * live <= 3 * h->total_tiles) {
+                HIP_TRY(batch_set_lists(h, active));
+                HIP_TRY(hipMemcpyAsync(h->d_pairs, h->pairs.data(), sizeof(BatchPair) * h->B, hipMemcpyHostToDevice,
+                                       h->cap));
+                HIP_TRY(hipStreamSynchronize(h->cap));
+                batch_drop_graphs(h);
+                ba.total_tiles = h->total_tiles;
+                ba.total_mtiles = h->total_mtiles;
+            }
+        }
     }
     return OMT_OK;
 }
@@ -1435,8 +1540,8 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
     h->ws = static_cast<char *>(workspace);
     h->comp = comp;
     h->dtype = dtype;
-    h->total_tiles = L.total_tiles;
-    h->total_mtiles = L.total_mtiles;
+    h->total_tiles = h->full_tiles = L.total_tiles;
+    h->total_mtiles = h->full_mtiles = L.total_mtiles;
     h->d_pairs = reinterpret_cast<BatchPair *>(h->ws + L.off_pairs);
     h->d_state = reinterpret_cast<BatchPairState *>(h->ws + L.off_state);
     h->d_tile_pair = reinterpret_cast<int *>(h->ws + L.off_tp);
@@ -1534,6 +1639,11 @@ omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, in
         }
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->total_tiles != h->full_tiles || h->total_mtiles != h->full_mtiles) {
+        // a previous solve dropped stopped problems: every problem runs again
+        HIP_TRY(batch_set_lists(h, std::vector<char>(h->B, 1)));
+        batch_drop_graphs(h);
+    }
     HIP_TRY(hipMemcpyAsync(h->d_pairs, h->pairs.data(), sizeof(BatchPair) * h->B, hipMemcpyHostToDevice, h->cap));
     BatchArgs ba;
     ba.pairs = h->d_pairs;
@@ -1636,5 +1746,380 @@ const char *omt_strerror(omt_status s)
 const char *omt_last_error(void) { return g_last_error.c_str(); }
 
 int32_t omt_version(void) { return 1; }
+
+}  // extern "C"
+
+// ================================================================== matrix OMT
+
+struct omt_mctx {
+    omt_ctx *c;          // the problem in coordinates
+    int k, K, Ks, l;     // matrix order, coordinates of Phi and of one W_s, matrices L_s
+    bool real;
+    int dtype;
+    int64_t npix;
+    hipStream_t stream;
+    char *stage;         // npix * max(2K, l Ks) values: packed data, unpacked outputs
+};
+
+namespace {
+
+using cplx = std::complex<double>;
+
+// Orthonormal basis (Hilbert-Schmidt inner product) of the Hermitian (herm)
+// or skew-Hermitian k x k matrices, in the coordinate order of the kernels:
+// diagonal first (skew: i E_aa, complex only), then for a < b the real pair
+// (E_ab +- E_ba)/sqrt2 and, complex only, the imaginary one i(E_ab -+ E_ba)/sqrt2.
+std::vector<std::vector<cplx>> matrix_basis(int k, bool real, bool herm)
+{
+    std::vector<std::vector<cplx>> B;
+    const double r = std::sqrt(0.5);
+    if (herm || !real)
+        for (int a = 0; a < k; ++a) {
+            std::vector<cplx> E(k * k, 0.0);
+            E[a * k + a] = herm ? cplx(1.0, 0.0) : cplx(0.0, 1.0);
+            B.push_back(E);
+        }
+    for (int a = 0; a < k; ++a)
+        for (int b = a + 1; b < k; ++b) {
+            std::vector<cplx> E(k * k, 0.0);
+            E[a * k + b] = r;
+            E[b * k + a] = herm ? r : -r;
+            B.push_back(E);
+            if (!real) {
+                std::vector<cplx> F(k * k, 0.0);
+                F[a * k + b] = cplx(0.0, r);
+                F[b * k + a] = herm ? cplx(0.0, -r) : cplx(0.0, r);
+                B.push_back(F);
+            }
+        }
+    return B;
+}
+
+double hs_dot(const std::vector<cplx> &X, const std::vector<cplx> &Y)
+{
+    double s = 0.0;
+    for (size_t q = 0; q < X.size(); ++q) s += (X[q] * std::conj(Y[q])).real();
+    return s;
+}
+
+struct MatrixSpec {
+    int k, K, Ks, l;
+    bool real;
+};
+
+omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &ms)
+{
+    if (!p) return fail(OMT_EINVAL, "params is NULL");
+    if (p->m < 2 || p->n < 2) return fail(OMT_EINVAL, "grid must be at least 2 x 2 (got %d x %d)", p->m, p->n);
+    if ((int64_t)p->m * p->n > (int64_t)1 << 31) return fail(OMT_EINVAL, "grid too large");
+    if (p->k < 2) return fail(OMT_EINVAL, "matrix order k must be >= 2 (got %d)", p->k);
+    if (p->n_L < 1 || !p->L) return fail(OMT_EINVAL, "need at least one matrix L_s");
+    if (p->real != 0 && p->real != 1) return fail(OMT_EINVAL, "real must be 0 or 1");
+    if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(OMT_EINVAL, "alpha must be > 0");
+    if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(OMT_EINVAL, "tau must be > 0");
+    if (p->mu < 0.0 || p->nu < 0.0 || p->h < 0.0 || !std::isfinite(p->mu) || !std::isfinite(p->nu) ||
+        !std::isfinite(p->h))
+        return fail(OMT_EINVAL, "mu, nu, h must be finite and >= 0");
+    if (p->unorm < 0 || p->unorm > 2 || p->wnorm < 0 || p->wnorm > 2) return fail(OMT_EINVAL, "unknown norm");
+    if (p->unorm == OMT_M_NUC || p->wnorm == OMT_M_NUC)
+        return fail(OMT_EUNSUPPORTED, "nuclear norms are not compiled into the matrix kernels");
+    if (p->dtype != OMT_F32 && p->dtype != OMT_F64) return fail(OMT_EINVAL, "unknown dtype %d", p->dtype);
+    if (p->rows_per_wave < 0) return fail(OMT_EINVAL, "rows_per_wave must be >= 0");
+    const int k = p->k, l = p->n_L;
+    const bool real = p->real != 0;
+    ms.k = k;
+    ms.l = l;
+    ms.real = real;
+    ms.K = real ? k * (k + 1) / 2 : k * k;
+    ms.Ks = real ? k * (k - 1) / 2 : k * k;
+    const int lc = l * ms.Ks;
+    if (ms.K > KMAX || matrix_bucket(ms.K) == 0 || lc > matrix_bucket(ms.K))
+        return fail(OMT_EUNSUPPORTED, "%s k = %d with %d matrices L_s is not compiled", real ? "real" : "complex", k, l);
+    // L: Hermitian (real symmetric in the real mode)
+    std::vector<std::vector<cplx>> L(l, std::vector<cplx>(k * k));
+    double big = 0.0;
+    for (int s = 0; s < l; ++s)
+        for (int q = 0; q < k * k; ++q) {
+            L[s][q] = cplx(p->L[2 * (s * k * k + q)], p->L[2 * (s * k * k + q) + 1]);
+            if (!std::isfinite(L[s][q].real()) || !std::isfinite(L[s][q].imag()))
+                return fail(OMT_EINVAL, "L_%d has a non-finite entry", s);
+            big = std::max(big, std::abs(L[s][q]));
+        }
+    if (!(big > 0.0)) return fail(OMT_EGRAPH, "every L_s is zero");
+    for (int s = 0; s < l; ++s)
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+                if (std::abs(L[s][a * k + b] - std::conj(L[s][b * k + a])) > 1e-12 * big)
+                    return fail(OMT_EINVAL, "L_%d is not Hermitian", s);
+                if (real && L[s][a * k + b].imag() != 0.0)
+                    return fail(OMT_EINVAL, "L_%d is not real (real mode)", s);
+            }
+    // the operator grad_L in coordinates: G[(s, q)][c] = <S_q, L_s H_c - H_c L_s>
+    auto coord_op = [&](bool rl, int &nK, int &nKs) {
+        const auto HB = matrix_basis(k, rl, true), SB = matrix_basis(k, rl, false);
+        nK = int(HB.size());
+        nKs = int(SB.size());
+        std::vector<double> G(size_t(l) * nKs * nK, 0.0);
+        for (int c = 0; c < nK; ++c)
+            for (int s = 0; s < l; ++s) {
+                std::vector<cplx> Z(k * k, 0.0);
+                for (int a = 0; a < k; ++a)
+                    for (int b = 0; b < k; ++b) {
+                        cplx v = 0.0;
+                        for (int q = 0; q < k; ++q)
+                            v += L[s][a * k + q] * HB[c][q * k + b] - HB[c][a * k + q] * L[s][q * k + b];
+                        Z[a * k + b] = v;
+                    }
+                for (int q = 0; q < nKs; ++q) G[size_t(s * nKs + q) * nK + c] = hs_dot(SB[q], Z);
+            }
+        return G;
+    };
+    int gK = 0, gKs = 0;
+    const std::vector<double> G = coord_op(real, gK, gKs);
+    // -Delta_L = G^T G on all Hermitian matrices (the k^2 x k^2 matrix of
+    // Sec. 7.3, also in the real mode): its spectrum gives nu, and its kernel
+    // must be the multiples of I (the standing assumption of Sec. 4.1)
+    int fK = 0, fKs = 0;
+    const std::vector<double> Gf = coord_op(false, fK, fKs);
+    const int fl = l * fKs;
+    std::vector<double> A(size_t(fK) * fK, 0.0);
+    for (int a = 0; a < fK; ++a)
+        for (int b = 0; b < fK; ++b) {
+            double v = 0.0;
+            for (int e = 0; e < fl; ++e) v += Gf[size_t(e) * fK + a] * Gf[size_t(e) * fK + b];
+            A[a * fK + b] = v;
+        }
+    const std::vector<double> ev = jacobi_eigenvalues(A, fK);
+    double lmax = 0.0;
+    for (double v : ev) lmax = std::max(lmax, v);
+    int nker = 0;
+    for (double v : ev)
+        if (v <= 1e-10 * lmax) ++nker;
+    if (nker != 1)
+        return fail(OMT_EGRAPH, "grad_L annihilates a %d-dimensional space; the method needs exactly the multiples of I",
+                    nker);
+
+    r = Resolved();
+    r.m = p->m;
+    r.n = p->n;
+    r.k = ms.K;
+    r.l = lc;
+    r.gk = G_MATRIX;
+    r.lb = matrix_bucket(ms.K);
+    r.alpha = p->alpha;
+    r.tau = p->tau;
+    r.eps = 0.0;
+    r.unorm = p->unorm == OMT_M_FRO ? 2 : 3;
+    r.wnorm = p->wnorm == OMT_M_FRO ? 1 : 2;
+    r.dtype = p->dtype;
+    r.comp = (p->flags & OMT_FLAG_COMPENSATED_PHI) && p->dtype == OMT_F32;
+    r.tblock = 1;
+    r.rows = p->rows_per_wave;
+    r.h = p->h > 0.0 ? p->h : 1.0 / double(std::max(r.m, r.n) - 1);
+    r.lmax = lmax;
+    const double h2 = r.h * r.h;
+    r.mu = p->mu > 0.0 ? p->mu : h2 / (32.0 * r.tau);
+    r.nu = p->nu > 0.0 ? p->nu : 1.0 / (4.0 * r.tau * lmax);
+    if (p->mu > 0.0 || p->nu > 0.0) {
+        const double cond = r.tau * r.mu * 8.0 / h2 + r.tau * r.nu * lmax;
+        if (!(cond < 1.0))
+            return fail(OMT_ESTEP, "tau mu 8/h^2 + tau nu lambda_max = %g must be < 1 (Sec. 7.3)", cond);
+    }
+    r.matrix = true;
+    r.gmat.assign(KMAX * LMAX, 0.0);
+    for (int c = 0; c < ms.K; ++c)
+        for (int e = 0; e < lc; ++e) r.gmat[c * LMAX + e] = G[size_t(e) * ms.K + c];
+    // grouped entry-wise norm: diagonal coordinates weigh 1; an off-diagonal
+    // pair (X_ab, X_ba) weighs 2 |X_ab| = sqrt2 |coordinates|
+    const int nd = k;
+    r.uwt.assign(ms.K, 0.0);
+    for (int c = 0; c < ms.K; ++c) r.uwt[c] = c < nd ? 1.0 : (real || (c - nd) % 2 == 0 ? std::sqrt(2.0) : 0.0);
+    r.wwt.assign(lc, 0.0);
+    const int snd = real ? 0 : k;
+    for (int s = 0; s < l; ++s)
+        for (int q = 0; q < ms.Ks; ++q)
+            r.wwt[s * ms.Ks + q] = q < snd ? 1.0 : (real || (q - snd) % 2 == 0 ? std::sqrt(2.0) : 0.0);
+    // mass: only the trace is conserved; the diagonal coordinates form the
+    // one class whose mean is removed
+    r.cls.assign(ms.K, -1);
+    for (int c = 0; c < nd; ++c) r.cls[c] = 0;
+    r.ncls = 1;
+    return OMT_OK;
+}
+
+size_t matrix_stage_bytes(const Resolved &r, const MatrixSpec &ms)
+{
+    const size_t per = size_t(std::max(2 * ms.K, ms.l * ms.Ks));
+    return align256(size_t(r.m) * r.n * per * (r.dtype == OMT_F64 ? 8 : 4));
+}
+
+hipError_t matrix_xfer(const omt_mctx *h, const void *src, void *dst, bool herm, bool pack, int count, int cstride,
+                       int coff)
+{
+    MatrixXferArgs a;
+    a.src = src;
+    a.dst = dst;
+    a.dtype = h->dtype;
+    a.npix = h->npix;
+    a.k = h->k;
+    a.real = h->real ? 1 : 0;
+    a.herm = herm ? 1 : 0;
+    a.pack = pack ? 1 : 0;
+    a.count = count;
+    a.cstride = cstride;
+    a.coff = coff;
+    return launch_matrix_xfer(a, h->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+omt_status omt_matrix_params_init(omt_matrix_params *p)
+{
+    if (!p) return fail(OMT_EINVAL, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->alpha = 1.0;
+    p->tau = 1.0;
+    p->unorm = OMT_M_FRO;
+    p->wnorm = OMT_M_L1;
+    p->dtype = OMT_F32;
+    return OMT_OK;
+}
+
+omt_status omt_matrix_resolve(const omt_matrix_params *p, double *h, double *mu, double *nu, double *lambda_max,
+                              int32_t *coords, int32_t *w_coords)
+{
+    Resolved r;
+    MatrixSpec ms;
+    omt_status s = resolve_matrix(p, r, ms);
+    if (s != OMT_OK) return s;
+    if (h) *h = r.h;
+    if (mu) *mu = r.mu;
+    if (nu) *nu = r.nu;
+    if (lambda_max) *lambda_max = r.lmax;
+    if (coords) *coords = ms.K;
+    if (w_coords) *w_coords = ms.l * ms.Ks;
+    return OMT_OK;
+}
+
+omt_status omt_matrix_workspace_bytes(const omt_matrix_params *p, size_t *bytes)
+{
+    if (!bytes) return fail(OMT_EINVAL, "bytes is NULL");
+    Resolved r;
+    MatrixSpec ms;
+    omt_status s = resolve_matrix(p, r, ms);
+    if (s != OMT_OK) return s;
+    *bytes = align256(make_layout(r).total) + matrix_stage_bytes(r, ms);
+    return OMT_OK;
+}
+
+omt_status omt_matrix_create(const omt_matrix_params *p, const void *Lambda0, const void *Lambda1, void *workspace,
+                             size_t ws_bytes, void *stream, omt_matrix_handle *out)
+{
+    if (!out) return fail(OMT_EINVAL, "out is NULL");
+    *out = nullptr;
+    Resolved r;
+    MatrixSpec ms;
+    omt_status s = resolve_matrix(p, r, ms);
+    if (s != OMT_OK) return s;
+    if (!Lambda0 || !Lambda1) return fail(OMT_EINVAL, "Lambda0 / Lambda1 is NULL");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(OMT_EINVAL, "workspace missing or not 256-byte aligned");
+    const size_t core = align256(make_layout(r).total), need = core + matrix_stage_bytes(r, ms);
+    if (ws_bytes < need) return fail(OMT_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    omt_mctx *h = new omt_mctx();
+    h->c = nullptr;
+    h->k = ms.k;
+    h->K = ms.K;
+    h->Ks = ms.Ks;
+    h->l = ms.l;
+    h->real = ms.real;
+    h->dtype = r.dtype;
+    h->npix = int64_t(r.m) * r.n;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->stage = static_cast<char *>(workspace) + core;
+    // pack both densities into coordinates (two halves of the staging area),
+    // then set up the coordinate problem from them
+    const size_t half = size_t(h->npix) * ms.K * (r.dtype == OMT_F64 ? 8 : 4);
+    hipError_t e = matrix_xfer(h, Lambda0, h->stage, true, true, 1, 1, 0);
+    if (e == hipSuccess) e = matrix_xfer(h, Lambda1, h->stage + half, true, true, 1, 1, 0);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(OMT_EDEVICE, "packing: %s", hipGetErrorString(e));
+    }
+    s = create_resolved(r, h->stage, h->stage + half, workspace, core, stream, &h->c);
+    if (s != OMT_OK) {
+        delete h;
+        return s;
+    }
+    *out = h;
+    return OMT_OK;
+}
+
+omt_status omt_matrix_solve(omt_matrix_handle h, int64_t max_iters, double tol, int32_t check_every, omt_info *info)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    return omt_solve(h->c, max_iters, tol, check_every, info);
+}
+
+omt_status omt_matrix_distance(omt_matrix_handle h, double *M, omt_info *info)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    return omt_distance(h->c, M, info);
+}
+
+omt_status omt_matrix_grad(omt_matrix_handle h, void *d0, void *d1)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    const size_t half = size_t(h->npix) * h->K * (h->dtype == OMT_F64 ? 8 : 4);
+    omt_status s = omt_grad(h->c, d0 ? h->stage : nullptr, d1 ? h->stage + half : nullptr);
+    if (s != OMT_OK) return s;
+    if (d0) HIP_TRY(matrix_xfer(h, h->stage, d0, true, false, 1, 1, 0));
+    if (d1) HIP_TRY(matrix_xfer(h, h->stage + half, d1, true, false, 1, 1, 0));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return OMT_OK;
+}
+
+omt_status omt_matrix_get_state(omt_matrix_handle h, void *Phi, void *Ux, void *Uy, void *W)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    if (Phi) {
+        omt_status s = omt_get_state(h->c, h->stage, nullptr, nullptr);
+        if (s != OMT_OK) return s;
+        HIP_TRY(matrix_xfer(h, h->stage, Phi, true, false, 1, 1, 0));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    if (Ux || Uy) {
+        // u arrives as m x n x K x 2 (x and y interleaved)
+        omt_status s = omt_get_state(h->c, nullptr, h->stage, nullptr);
+        if (s != OMT_OK) return s;
+        if (Ux) HIP_TRY(matrix_xfer(h, h->stage, Ux, true, false, 1, 2, 0));
+        if (Uy) HIP_TRY(matrix_xfer(h, h->stage, Uy, true, false, 1, 2, 1));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    if (W) {
+        omt_status s = omt_get_state(h->c, nullptr, nullptr, h->stage);
+        if (s != OMT_OK) return s;
+        HIP_TRY(matrix_xfer(h, h->stage, W, false, false, h->l, 1, 0));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    return OMT_OK;
+}
+
+omt_status omt_matrix_time_steps(omt_matrix_handle h, int32_t rows_per_wave, int64_t n, double *us_per_launch)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    return omt_time_steps(h->c, 1, rows_per_wave, n, us_per_launch);
+}
+
+omt_status omt_matrix_destroy(omt_matrix_handle h)
+{
+    if (h) {
+        if (h->c) omt_destroy(h->c);
+        delete h;
+    }
+    return OMT_OK;
+}
 
 }  // extern "C"

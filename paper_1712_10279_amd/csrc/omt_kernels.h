@@ -19,7 +19,18 @@ constexpr int NMET = 8;  // su, sw, sp, cross, primal, dual, mass, sum_phi
 // incidence structure at compile time; any other graph uses the dense
 // matrix M = D diag(1/c) with the edge count rounded up to a bucket (the
 // unused edges carry zero weight).
-enum GraphKind { G_NONE = 0, G_PATH = 1, G_COMPLETE = 2, G_DENSE = 3 };
+// G_MATRIX: the matrix method in orthonormal real coordinates of the
+// Hermitian / skew-Hermitian matrices: a dense operator plus the grouped
+// entry-wise norms (u norm 3, w norm 2) of that coordinate system.
+enum GraphKind { G_NONE = 0, G_PATH = 1, G_COMPLETE = 2, G_DENSE = 3, G_MATRIX = 4 };
+
+// Coordinates of the transfer variable compiled for a matrix problem with
+// K coordinates of the potential: K = 3 (real 2 x 2), 4 (complex 2 x 2) and
+// 6 (real 3 x 3), up to three matrices L_s (two for complex 2 x 2).
+inline int matrix_bucket(int K)
+{
+    return K == 3 ? 3 : K == 4 ? 8 : K == 6 ? 9 : 0;
+}
 
 inline int dense_bucket(int k, int l)
 {
@@ -55,6 +66,10 @@ struct StepArgs {
     double eps;            // quadratic regularisation weight (objective)
     R ic[LMAX];            // 1 / c_e
     R gm[KMAX * LMAX];     // dense graphs: M = D diag(1/c), row c, column e at gm[c * LMAX + e]
+    // grouped norms (G_MATRIX): weight of the group that starts at this
+    // coordinate; 0 marks the second coordinate of a two-coordinate group
+    R uwt[KMAX];
+    R wwt[LMAX];
 };
 
 struct StepLaunch {
@@ -187,5 +202,22 @@ struct XferArgs {
 hipError_t launch_xfer(const XferArgs &a, hipStream_t s);
 
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+
+// Matrices <-> orthonormal real coordinates of the matrix method.  Per pixel
+// `count` k x k matrices (complex (re, im) pairs, or real entries when real
+// is set) against `count` groups of ncoord coordinates; coordinate c of
+// group g at pixel p sits at ((p * count + g) * ncoord + c) * cstride + coff.
+// Hermitian coordinates: X_aa, then for a < b sqrt2 Re X_ab (and sqrt2
+// Im X_ab); skew-Hermitian: Im X_aa (complex only), then the same pairs.
+// Packing reads the upper triangle and the diagonal only.
+struct MatrixXferArgs {
+    const void *src;
+    void *dst;
+    int dtype;
+    int64_t npix;
+    int k, real, herm, pack;
+    int count, cstride, coff;
+};
+hipError_t launch_matrix_xfer(const MatrixXferArgs &a, hipStream_t s);
 
 }  // namespace omt

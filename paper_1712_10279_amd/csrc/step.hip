@@ -85,7 +85,7 @@ hipError_t occ_T(const StepLaunch &Lc, int *blocks)
 {
     if (Lc.dtype == 1) return occ_one<double, GK, L, 1, false>(blocks);
     if (Lc.T == 1) return Lc.comp ? occ_one<float, GK, L, 1, true>(blocks) : occ_one<float, GK, L, 1, false>(blocks);
-    if constexpr (GK != G_DENSE) {
+    if constexpr (GK != G_DENSE && GK != G_MATRIX) {
         switch (Lc.T) {
             case 2: return Lc.comp ? occ_one<float, GK, L, 2, true>(blocks) : occ_one<float, GK, L, 2, false>(blocks);
 #if OMT_K <= 5
@@ -130,7 +130,7 @@ hipError_t dispatch_T(const StepLaunch &Lc)
         return hipErrorInvalidValue;
     }
     if (Lc.T == 1) return Lc.comp ? launch_one<float, GK, L, 1, true>(Lc) : launch_one<float, GK, L, 1, false>(Lc);
-    if constexpr (GK != G_DENSE) {
+    if constexpr (GK != G_DENSE && GK != G_MATRIX) {
         switch (Lc.T) {
             case 2: return Lc.comp ? launch_one<float, GK, L, 2, true>(Lc) : launch_one<float, GK, L, 2, false>(Lc);
 #if OMT_K <= 5
@@ -147,6 +147,8 @@ hipError_t dispatch_T(const StepLaunch &Lc)
 
 constexpr int L_TREE = OMT_K - 1;
 constexpr int L_FULL = OMT_K * (OMT_K - 1) / 2;
+// matrix problems compiled for this coordinate count (0: none)
+constexpr int L_MAT = OMT_K == 3 ? 3 : OMT_K == 4 ? 8 : OMT_K == 6 ? 9 : 0;
 
 }  // namespace
 
@@ -164,6 +166,9 @@ hipError_t OMT_CAT(launch_step_k, OMT_K)(const StepLaunch &Lc)
     if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return dispatch_T<G_DENSE, L_TREE>(Lc);
     if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return dispatch_T<G_DENSE, L_FULL>(Lc);
 #endif
+#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
+    if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return dispatch_T<G_MATRIX, L_MAT>(Lc);
+#endif
     return hipErrorInvalidValue;
 }
 
@@ -177,6 +182,9 @@ hipError_t OMT_CAT(launch_metrics_k, OMT_K)(const StepLaunch &Lc, int ncolw, int
     if (Lc.gk == G_COMPLETE && Lc.lb == L_FULL) return dispatch_met<G_COMPLETE, L_FULL>(Lc, ncolw, ntiles, partials);
     if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return dispatch_met<G_DENSE, L_TREE>(Lc, ncolw, ntiles, partials);
     if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return dispatch_met<G_DENSE, L_FULL>(Lc, ncolw, ntiles, partials);
+#endif
+#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
+    if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return dispatch_met<G_MATRIX, L_MAT>(Lc, ncolw, ntiles, partials);
 #endif
     return hipErrorInvalidValue;
 }
@@ -192,6 +200,9 @@ hipError_t OMT_CAT(step_blocks_per_cu_k, OMT_K)(const StepLaunch &Lc, int *block
     if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return occ_T<G_DENSE, L_TREE>(Lc, blocks);
     if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return occ_T<G_DENSE, L_FULL>(Lc, blocks);
 #endif
+#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
+    if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return occ_T<G_MATRIX, L_MAT>(Lc, blocks);
+#endif
     return hipErrorInvalidValue;
 }
 
@@ -201,9 +212,10 @@ bool OMT_CAT(step_supported_k, OMT_K)(int dtype, int gk, int lb, int T, bool com
     ok = ok || (OMT_K >= 2 && gk == G_PATH && lb == L_TREE);
     ok = ok || (OMT_K >= 3 && gk == G_COMPLETE && lb == L_FULL);
     ok = ok || (OMT_K >= 3 && gk == G_DENSE && (lb == L_TREE || lb == L_FULL));
+    ok = ok || (L_MAT > 0 && gk == G_MATRIX && lb == L_MAT);
     if (!ok) return false;
     if (dtype == 1) return T == 1 && !comp;
-    if (gk == G_DENSE) return T == 1;
+    if (gk == G_DENSE || gk == G_MATRIX) return T == 1;
     return t_ok(T);
 }
 

@@ -20,19 +20,45 @@ __device__ __forceinline__ double lane_prev(double v) { return __shfl_up(v, 1u, 
 #ifndef OMT_STREAM_NT
 #define OMT_STREAM_NT 0
 #endif
+//
+// Every field access goes through a global-address-space pointer.  The
+// batched kernel reads its field pointers from a table in memory, where the
+// compiler cannot infer the address space and would otherwise emit flat
+// accesses, which wait on both the vector-memory and the LDS counters.
+#define OMT_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const OMT_GLOBAL T *gptr(const T *p)
+{
+    return (const OMT_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ OMT_GLOBAL T *gptr(T *p)
+{
+    return (OMT_GLOBAL T *)p;
+}
+template <typename R>
+__device__ __forceinline__ R ld_field(const R *p)
+{
+    return *gptr(p);
+}
+template <typename R>
+__device__ __forceinline__ void st_field(R *p, R v)
+{
+    *gptr(p) = v;
+}
 template <typename R>
 __device__ __forceinline__ R ld_stream(const R *p)
 {
-    if constexpr (OMT_STREAM_NT != 0) return __builtin_nontemporal_load(p);
-    return *p;
+    if constexpr (OMT_STREAM_NT != 0) return __builtin_nontemporal_load(gptr(p));
+    return *gptr(p);
 }
 template <typename R>
 __device__ __forceinline__ void st_stream(R *p, R v)
 {
     if constexpr (OMT_STREAM_NT != 0)
-        __builtin_nontemporal_store(v, p);
+        __builtin_nontemporal_store(v, gptr(p));
     else
-        *p = v;
+        *gptr(p) = v;
 }
 
 // value of lane L (a wave-uniform result)
@@ -103,6 +129,24 @@ __device__ __forceinline__ void shrink_w(int wnorm, R (&w)[L], R t)
     }
 }
 
+// Grouped entry-wise norm sum_g wt_g ||x_g||_2 over groups of one or two
+// coordinates (wt > 0 starts a group; a following 0 joins it): the factor
+// of the shrink with threshold wt_g * t for every coordinate.
+template <typename R, int N>
+__device__ __forceinline__ void group_scales(const R *wt, const R (&x)[N], R t, R (&sc)[N])
+{
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        if (wt[c] > R(0)) {
+            const bool pair = (c + 1 < N) && wt[c + 1] == R(0);
+            const R r = pair ? sqrt(x[c] * x[c] + x[c + 1] * x[c + 1]) : fabs(x[c]);
+            const R s = shrink_scale<R>(r, wt[c] * t);
+            sc[c] = s;
+            if (c + 1 < N && pair) sc[c + 1] = s;
+        }
+    }
+}
+
 // ------------------------------------------------------------ channel graph
 
 // Endpoints (a_e, b_e), a_e < b_e, of edge e of the compiled graph kinds.
@@ -158,7 +202,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
             R s = R(0);
-            if constexpr (GK == G_DENSE) {
+            if constexpr (GK == G_DENSE || GK == G_MATRIX) {
 #pragma unroll
                 for (int c = 0; c < K; ++c) {
                     s = s + a.gm[c * LMAX + e] * pA[c];
@@ -172,7 +216,18 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
                 wt[e] = w[e] + a.nu * (s * a.ic[e]);
             }
         }
-        shrink_w<R, LA>(a.wnorm, wt, a.anu);
+        if constexpr (GK == G_MATRIX) {
+            if (a.wnorm == 2) {
+                R sc[LA];
+                group_scales<R, LA>(a.wwt, wt, a.anu, sc);
+#pragma unroll
+                for (int e = 0; e < LA; ++e) wt[e] = wt[e] * sc[e];
+            } else {
+                shrink_w<R, LA>(a.wnorm, wt, a.anu);
+            }
+        } else {
+            shrink_w<R, LA>(a.wnorm, wt, a.anu);
+        }
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
             wt[e] = wt[e] * a.wreg;  // regularised prox (factor 1 without regularisation)
@@ -238,6 +293,26 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         s_all = shrink_scale<R>(sqrt(r2), a.mu);
         s_left = shrink_scale<R>(sqrt(r2l), a.mu);
     }
+    // grouped entry-wise norm of the matrix kinds: per-coordinate factors of
+    // this pixel and, in the aligned mode, of the pixel left of the strip
+    R gsx[K], gsy[K], gsxl[K], gsyl[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) gsx[c] = gsy[c] = gsxl[c] = gsyl[c] = R(0);
+    if constexpr (GK == G_MATRIX) {
+        if (a.unorm == 3) {
+            R qx[K], qy[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) utilde(c, qx[c], qy[c]);
+            group_scales<R, K>(a.uwt, qx, a.mu, gsx);
+            group_scales<R, K>(a.uwt, qy, a.mu, gsy);
+            if (ALN) {
+#pragma unroll
+                for (int c = 0; c < K; ++c) utilde_left(c, qx[c], qy[c]);
+                group_scales<R, K>(a.uwt, qx, a.mu, gsxl);
+                group_scales<R, K>(a.uwt, qy, a.mu, gsyl);
+            }
+        }
+    }
     auto shrink_pair = [&](R tx, R ty, R sblock, R &bx, R &by) {
         if (a.unorm == 0) {  // sum over channels of ||(u_x, u_y)||_2 (App. B shrink_2 per channel)
             const R s = shrink_scale<R>(sqrt(tx * tx + ty * ty), a.mu);
@@ -257,7 +332,12 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
     for (int c = 0; c < K; ++c) {
         R tx, ty, bx, by;
         utilde(c, tx, ty);
-        shrink_pair(tx, ty, s_all, bx, by);
+        if (GK == G_MATRIX && a.unorm == 3) {
+            bx = tx * gsx[c];
+            by = ty * gsy[c];
+        } else {
+            shrink_pair(tx, ty, s_all, bx, by);
+        }
         bx = bx * a.ureg;  // regularised prox (factor 1 without regularisation)
         by = by * a.ureg;
         if (!lane_ok) bx = by = R(0);
@@ -267,7 +347,12 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         if (ALN) {
             R ex, ey, ebx, eby;
             utilde_left(c, ex, ey);
-            shrink_pair(ex, ey, s_left, ebx, eby);
+            if (GK == G_MATRIX && a.unorm == 3) {
+                ebx = ex * gsxl[c];
+                eby = ey * gsyl[c];
+            } else {
+                shrink_pair(ex, ey, s_left, ebx, eby);
+            }
             eby = eby * a.ureg;
             const R el = E.hasL ? R(2) * eby - lane_get(E.Luy, c) : R(0);
             if (lane == 0) ubl = el;
@@ -278,7 +363,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         if constexpr (L > 0) {
 #pragma unroll
             for (int e = 0; e < LA; ++e) {
-                if constexpr (GK == G_DENSE) {
+                if constexpr (GK == G_DENSE || GK == G_MATRIX) {
                     dg = dg + a.gm[c * LMAX + e] * wb[e];
                 } else {
                     if (edge_a<GK, K>(e) == c) dg = dg + a.ic[e] * wb[e];
@@ -306,7 +391,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         uyO[c] = by;
         if (st) {
             st_stream(&a.phi_out[c * P + o], po);
-            if (COMP) a.plo_out[c * P + o] = float(pol);
+            if (COMP) st_field(&a.plo_out[c * P + o], float(pol));
             st_stream(&a.u_out[c * P + o], bx);
             st_stream(&a.u_out[(K + c) * P + o], by);
         }
@@ -355,10 +440,10 @@ __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int 
     const bool hl = lane < K;
     const int hc = hl ? lane : 0;
     auto ld_edge = [&](int col, int r, const R *base, int plane0) -> R {
-        return base[(plane0 + hc) * P + (int64_t)r * pitch + col];
+        return ld_field(&base[(plane0 + hc) * P + (int64_t)r * pitch + col]);
     };
     auto ld_edge_lo = [&](int col, int r) -> R {
-        return R(a.plo_in[hc * P + (int64_t)r * pitch + col]);
+        return R(ld_field(&a.plo_in[hc * P + (int64_t)r * pitch + col]));
     };
     // next-row values (prefetched) of the edge columns
     R nRA = R(0), nRAl = R(0);                    // phi(r, jR)
@@ -370,8 +455,8 @@ __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int 
     auto load_phi = [&](int r, R (&hi)[K], R (&lo)[K]) {
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-            hi[c] = (jin && r < a.m) ? phi[c * P + (int64_t)r * pitch] : R(0);
-            lo[c] = (COMP && jin && r < a.m) ? R(plo[c * P + (int64_t)r * pitch]) : R(0);
+            hi[c] = (jin && r < a.m) ? ld_field(&phi[c * P + (int64_t)r * pitch]) : R(0);
+            lo[c] = (COMP && jin && r < a.m) ? R(ld_field(&plo[c * P + (int64_t)r * pitch])) : R(0);
         }
     };
     // a single-iteration launch needs no w or f on its top halo row

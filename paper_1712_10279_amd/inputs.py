@@ -158,3 +158,70 @@ def random_pair(seed: int, m: int, n: int, k: int, bumps: int = 3, floor: float 
     lo = max(1.0, min(m, n) / 12.0)
     hi = max(2.0, min(m, n) / 4.0)
     return pair(100, seed, m, n, k, bumps, lo, hi, floor)
+
+
+# ------------------------------------------------------------- matrix method
+#
+# The paper's diffusion-tensor densities (Sec. 8.2) are not available.
+# Stand-ins of the same kind: every pixel carries a positive semidefinite
+# k x k matrix, the sum of a few Gaussian bumps, each bump with its own
+# "ellipsoid" (a random positive definite matrix of unit trace: Q diag(d) Q^*
+# with Q from the QR factorisation of a Gaussian matrix, real or complex,
+# and d uniform in [0.1, 1] normalised), plus floor * I; the whole field has
+# unit total trace (Sec. 4.2).
+
+# the two 3 x 3 matrices of the diffusion-tensor example (Sec. 8.2)
+L_DTI = np.array([[[1, 0, 0], [0, 2, 0], [0, 0, 0]], [[1, 1, 1], [1, 0, 0], [1, 0, 0]]], dtype=np.float64)
+# a pair of Hermitian 2 x 2 matrices whose commutant is the multiples of I
+L_PAULI_XZ = np.array([[[0, 1], [1, 0]], [[1, 0], [0, -1]]], dtype=np.complex128)
+
+
+def _ellipsoid(rng, k, real):
+    X = rng.normal(size=(k, k)) + (0 if real else 1j * rng.normal(size=(k, k)))
+    Q, _ = np.linalg.qr(X)
+    d = rng.uniform(0.1, 1.0, size=k)
+    d /= d.sum()
+    return (Q * d) @ Q.conj().T
+
+
+def matrix_field(rng, m, n, k, bumps, sig_lo, sig_hi, real, floor=1e-3, centres=None, shapes=None):
+    ii, jj = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    out = np.zeros((m, n, k, k), dtype=np.complex128)
+    for b in range(bumps):
+        ci, cj = centres[b] if centres is not None else (rng.uniform(0, m - 1), rng.uniform(0, n - 1))
+        sig = rng.uniform(sig_lo, sig_hi)
+        amp = rng.uniform(0.5, 1.5)
+        A = shapes[b] if shapes is not None else _ellipsoid(rng, k, real)
+        g = amp * np.exp(-((ii - ci) ** 2 + (jj - cj) ** 2) / (2.0 * sig * sig))
+        out += g[:, :, None, None] * A
+    out += floor * np.eye(k)
+    out /= np.trace(out.sum((0, 1))).real
+    return out.real.copy() if real else out
+
+
+def matrix_pair(seed, m, n, k, real, bumps=3, floor=1e-3):
+    """Two independent unit-trace matrix fields (small parity cases)."""
+    r0 = np.random.default_rng(np.random.SeedSequence([7, seed, 0]))
+    r1 = np.random.default_rng(np.random.SeedSequence([7, seed, 1]))
+    s = max(m, n)
+    return (matrix_field(r0, m, n, k, bumps, s / 12, s / 5, real, floor),
+            matrix_field(r1, m, n, k, bumps, s / 12, s / 5, real, floor))
+
+
+def dti_like(side=128, seed=0, bumps=6):
+    """Three real 3 x 3 fields in the manner of the paper's Lambda0, Lambda1,
+    Lambda2: Lambda1 has Lambda0's bump centres and widths with other
+    ellipsoids; Lambda2 has Lambda0's ellipsoids at other centres."""
+    rng = np.random.default_rng(np.random.SeedSequence([8, seed, side]))
+    cen0 = [(rng.uniform(side * 0.2, side * 0.8), rng.uniform(side * 0.2, side * 0.8)) for _ in range(bumps)]
+    cen2 = [(rng.uniform(side * 0.2, side * 0.8), rng.uniform(side * 0.2, side * 0.8)) for _ in range(bumps)]
+    sh0 = [_ellipsoid(rng, 3, True) for _ in range(bumps)]
+    sh1 = [_ellipsoid(rng, 3, True) for _ in range(bumps)]
+    state = rng.bit_generator.state
+
+    def field(cen, sh):
+        r = np.random.default_rng()
+        r.bit_generator.state = state  # same widths and amplitudes for all three
+        return matrix_field(r, side, side, 3, bumps, side / 32, side / 12, True, 1e-3, centres=cen, shapes=sh)
+
+    return {"lam0": field(cen0, sh0), "lam1": field(cen0, sh1), "lam2": field(cen2, sh0), "L": L_DTI}

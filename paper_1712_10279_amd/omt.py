@@ -35,6 +35,17 @@ class Params(C.Structure):
                 ("reg_eps", C.c_double)]
 
 
+M_FRO, M_L1, M_NUC = 0, 1, 2
+
+
+class MatrixParams(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("k", C.c_int32), ("n_L", C.c_int32),
+                ("L", C.POINTER(C.c_double)), ("real", C.c_int32),
+                ("alpha", C.c_double), ("tau", C.c_double), ("mu", C.c_double), ("nu", C.c_double),
+                ("h", C.c_double), ("unorm", C.c_int32), ("wnorm", C.c_int32), ("dtype", C.c_int32),
+                ("flags", C.c_int32), ("rows_per_wave", C.c_int32)]
+
+
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int64), ("residual", C.c_double), ("primal", C.c_double), ("dual", C.c_double),
                 ("rel_gap", C.c_double), ("mass_residual", C.c_double), ("R", C.c_double),
@@ -76,6 +87,18 @@ _SIGS = {
     "omt_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]),
     "omt_time_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_double)]),
+    "omt_matrix_params_init": (C.c_int, [C.POINTER(MatrixParams)]),
+    "omt_matrix_resolve": (C.c_int, [C.POINTER(MatrixParams)] + [C.POINTER(C.c_double)] * 4 +
+                           [C.POINTER(C.c_int32)] * 2),
+    "omt_matrix_workspace_bytes": (C.c_int, [C.POINTER(MatrixParams), C.POINTER(C.c_size_t)]),
+    "omt_matrix_create": (C.c_int, [C.POINTER(MatrixParams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                    C.c_void_p, C.POINTER(C.c_void_p)]),
+    "omt_matrix_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.POINTER(Info)]),
+    "omt_matrix_distance": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(Info)]),
+    "omt_matrix_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "omt_matrix_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "omt_matrix_time_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)]),
+    "omt_matrix_destroy": (C.c_int, [C.c_void_p]),
     "omt_strerror": (C.c_char_p, [C.c_int]),
     "omt_last_error": (C.c_char_p, []),
     "omt_version": (C.c_int32, []),
@@ -385,3 +408,106 @@ class BatchSolver:
         _check(lib().omt_batch_get_state(self._h, int(b), _ptr(phi), _ptr(u), _ptr(w) if l else C.c_void_p(0)),
                "omt_batch_get_state")
         return {"phi": phi, "u": u, "w": w[:, :, :l]}
+
+
+# ----------------------------------------------------------------- matrix OMT
+
+def make_matrix_params(m, n, L, real, alpha=1.0, tau=1.0, unorm=M_FRO, wnorm=M_L1, mu=0.0, nu=0.0, h=0.0,
+                       compensated=False, rows_per_wave=0, dtype=F32):
+    """(MatrixParams, keep-alive array) for the matrix C ABI; L is an
+    (l, k, k) real or complex array of Hermitian matrices."""
+    Lc = np.asarray(L)
+    if Lc.ndim == 2:
+        Lc = Lc[None]
+    Lc = np.ascontiguousarray(Lc.astype(np.complex128))
+    p = MatrixParams()
+    lib().omt_matrix_params_init(C.byref(p))
+    p.m, p.n, p.k, p.n_L = int(m), int(n), int(Lc.shape[1]), int(Lc.shape[0])
+    p.L = Lc.ctypes.data_as(C.POINTER(C.c_double))
+    p.real = 1 if real else 0
+    p.alpha, p.tau, p.mu, p.nu, p.h = float(alpha), float(tau), float(mu), float(nu), float(h)
+    p.unorm, p.wnorm, p.dtype = int(unorm), int(wnorm), int(dtype)
+    p.flags = FLAG_COMPENSATED_PHI if compensated else 0
+    p.rows_per_wave = int(rows_per_wave)
+    return p, Lc
+
+
+def matrix_resolve(m, n, L, real, **kw):
+    """(h, mu, nu, lambda_max(-Delta_L), coordinates of Phi, coordinates of W)."""
+    p, keep = make_matrix_params(m, n, L, real, **kw)
+    h, mu, nu, lm = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    K, KW = C.c_int32(), C.c_int32()
+    _check(lib().omt_matrix_resolve(C.byref(p), C.byref(h), C.byref(mu), C.byref(nu), C.byref(lm), C.byref(K),
+                                    C.byref(KW)), "omt_matrix_resolve")
+    return h.value, mu.value, nu.value, lm.value, K.value, KW.value
+
+
+class MatrixSolver:
+    """One matrix-OMT problem (omt_matrix_create ... omt_matrix_destroy).
+    Lambda0 / Lambda1: GPU tensors (m, n, k, k), complex64/complex128, or
+    float32/float64 in the real mode (real symmetric data and L)."""
+
+    def __init__(self, lam0, lam1, L, **kw):
+        torch = _torch()
+        a0, a1 = lam0.contiguous(), lam1.contiguous()
+        if not a0.is_cuda or a0.dtype != a1.dtype or a0.shape != a1.shape:
+            raise ValueError("Lambda0 / Lambda1 must be GPU tensors of one dtype and shape")
+        real = not a0.is_complex()
+        if a0.dtype in (torch.float64, torch.complex128):
+            dtype = F64
+        elif a0.dtype in (torch.float32, torch.complex64):
+            dtype = F32
+        else:
+            raise ValueError("unsupported dtype")
+        m, n, k = (int(x) for x in a0.shape[:3])
+        self.m, self.n, self.k, self.real = m, n, k, real
+        self.tdtype = a0.dtype
+        self.params, self._keep = make_matrix_params(m, n, L, real, dtype=dtype, **kw)
+        self.l = int(self.params.n_L)
+        nbytes = C.c_size_t()
+        _check(lib().omt_matrix_workspace_bytes(C.byref(self.params), C.byref(nbytes)), "omt_matrix_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=a0.device)
+        self.device = a0.device
+        self._in = (a0, a1)
+        h = C.c_void_p()
+        _check(lib().omt_matrix_create(C.byref(self.params), _ptr(a0), _ptr(a1), _ptr(self.workspace), nbytes.value,
+                                       _stream_ptr(), C.byref(h)), "omt_matrix_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.omt_matrix_destroy(h)
+            self._h = None
+
+    def solve(self, max_iters, tol=0.0, check_every=64, allow_notconv=True):
+        info = Info()
+        allow = (ENOTCONV,) if allow_notconv else ()
+        _check(lib().omt_matrix_solve(self._h, int(max_iters), float(tol), int(check_every), C.byref(info)),
+               "omt_matrix_solve", allow)
+        return info.as_dict()
+
+    def distance(self):
+        M, info = C.c_double(), Info()
+        _check(lib().omt_matrix_distance(self._h, C.byref(M), C.byref(info)), "omt_matrix_distance")
+        return M.value, info.as_dict()
+
+    def _mat(self, count=None):
+        torch = _torch()
+        shape = (self.m, self.n) + ((count,) if count else ()) + (self.k, self.k)
+        return torch.empty(shape, dtype=self.tdtype, device=self.device)
+
+    def grad(self):
+        d0, d1 = self._mat(), self._mat()
+        _check(lib().omt_matrix_grad(self._h, _ptr(d0), _ptr(d1)), "omt_matrix_grad")
+        return d0, d1
+
+    def get_state(self):
+        phi, ux, uy, w = self._mat(), self._mat(), self._mat(), self._mat(self.l)
+        _check(lib().omt_matrix_get_state(self._h, _ptr(phi), _ptr(ux), _ptr(uy), _ptr(w)), "omt_matrix_get_state")
+        return {"phi": phi, "ux": ux, "uy": uy, "w": w}
+
+    def time_steps(self, rows_per_wave, n):
+        us = C.c_double()
+        _check(lib().omt_matrix_time_steps(self._h, int(rows_per_wave), int(n), C.byref(us)), "omt_matrix_time_steps")
+        return us.value

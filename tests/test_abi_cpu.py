@@ -14,9 +14,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "omt.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(omt_[a-z_]+)\s*\(", src)))
+    names = set()
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hdr.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", hdr)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(omt_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -86,3 +90,39 @@ def test_status_strings():
     L = omt.lib()
     for s in range(10):
         assert L.omt_strerror(s)
+
+
+L_DTI = np.array([[[1, 0, 0], [0, 2, 0], [0, 0, 0]], [[1, 1, 1], [1, 0, 0], [1, 0, 0]]], float)
+PAULI = {"x": np.array([[0, 1], [1, 0]], complex), "y": np.array([[0, -1j], [1j, 0]]),
+         "z": np.array([[1, 0], [0, -1]], complex)}
+
+
+def test_matrix_step_sizes_and_coordinates():
+    import oracle.matrix as M
+    h, mu, nu, lm, K, KW = omt.matrix_resolve(40, 50, L_DTI, True, tau=3.0)
+    # lambda_max(-Delta_L) of the example matrices: the oracle's k^2 x k^2 matrix
+    assert lm == pytest.approx(M.lambda_max(L_DTI), rel=1e-12)
+    assert (K, KW) == (6, 6) and h == pytest.approx(1 / 49)
+    assert mu == pytest.approx(h * h / 96) and nu == pytest.approx(1 / (12 * lm))
+    L2 = np.stack([PAULI["x"], PAULI["z"]])
+    _, _, _, lm2, K2, KW2 = omt.matrix_resolve(10, 10, L2, False)
+    assert (K2, KW2) == (4, 8) and lm2 == pytest.approx(M.lambda_max(L2), rel=1e-12)
+    # a single L_s always commutes with itself, so the real 2 x 2 case takes two
+    _, _, _, lm3, K3, KW3 = omt.matrix_resolve(10, 10, np.stack([PAULI["x"].real, PAULI["z"].real]), True)
+    assert (K3, KW3) == (3, 2) and lm3 == pytest.approx(M.lambda_max(np.stack([PAULI["x"], PAULI["z"]])), rel=1e-12)
+
+
+@pytest.mark.parametrize("L,real,kw,status", [
+    (PAULI["x"][None], False, {}, omt.EGRAPH),            # sigma_x commutes with itself: ker is span(I, sigma_x)
+    (np.array([[[0, 1], [0, 0]]], complex), False, {}, omt.EINVAL),   # not Hermitian
+    (PAULI["y"][None], True, {}, omt.EINVAL),             # imaginary L in the real mode
+    (L_DTI, True, {"unorm": omt.M_NUC}, omt.EUNSUPPORTED),
+    (np.stack([np.eye(3), np.diag([1.0, 2, 3])]), True, {}, omt.EGRAPH),  # commuting diagonals
+    (np.stack([PAULI["x"], PAULI["z"], PAULI["y"]]), False, {}, omt.EUNSUPPORTED),  # 12 transfer coordinates
+    (L_DTI, True, {"tau": 0.0}, omt.EINVAL),
+    (L_DTI, True, {"mu": 1.0}, omt.ESTEP),
+])
+def test_matrix_invalid_parameters(L, real, kw, status):
+    with pytest.raises(omt.OMTError) as e:
+        omt.matrix_resolve(12, 12, L, real, **kw)
+    assert e.value.status == status

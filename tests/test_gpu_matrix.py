@@ -1,0 +1,129 @@
+"""Parity of the matrix-OMT HIP path (through the C ABI of
+include/omt_matrix.h) with the FP64 whole-matrix oracle (Sec. 4, Sec. 7.3).
+The GPU carries the matrices in orthonormal coordinates; the oracle works on
+complex k x k matrices, so agreement also checks the packing, the operator
+and the grouped norms."""
+import numpy as np
+import pytest
+
+import oracle.matrix as MO
+from gpu_util import cuda, note
+from paper_1712_10279_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+rng = np.random.default_rng(44)
+
+
+def _herm(k):
+    A = rng.normal(size=(k, k)) + 1j * rng.normal(size=(k, k))
+    return (A + A.conj().T) / 2
+
+
+CASES = {  # name: (m, n, k, real, L)
+    "dti_real_k3": (40, 70, 3, True, I.L_DTI),
+    "pauli_real_k2": (21, 130, 2, True, I.L_PAULI_XZ.real.copy()),
+    "complex_k2": (33, 65, 2, False, np.stack([I.L_PAULI_XZ[0] + 0.3 * _herm(2), I.L_PAULI_XZ[1]])),
+    "dti_plus_one_real_k3": (3, 130, 3, True, np.stack([I.L_DTI[0], I.L_DTI[1], np.diag([0.0, 1.0, -1.0])])),
+}
+
+
+def _dev(torch, a, real, f64):
+    if real:
+        return torch.as_tensor(np.ascontiguousarray(a.real), dtype=torch.float64 if f64 else torch.float32,
+                               device="cuda")
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.complex128 if f64 else torch.complex64,
+                           device="cuda")
+
+
+def _np(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def _solver(torch, case, f64=True, seed=5, **kw):
+    from paper_1712_10279_amd import omt
+    m, n, k, real, L = CASES[case]
+    lam0, lam1 = I.matrix_pair(seed, m, n, k, real)
+    if not f64:
+        # both sides see the inputs as rounded to the kernel's dtype
+        cast = np.float32 if real else np.complex64
+        lam0, lam1 = lam0.astype(cast).astype(np.complex128), lam1.astype(cast).astype(np.complex128)
+    s = omt.MatrixSolver(_dev(torch, lam0, real, f64), _dev(torch, lam1, real, f64), L, **kw)
+    return s, lam0, lam1, L
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("unorm,wnorm", [(MO.FRO, MO.L1), (MO.L1, MO.L1), (MO.FRO, MO.FRO), (MO.L1, MO.FRO)])
+def test_fp64_state_matches_oracle(case, unorm, wnorm):
+    torch = cuda()
+    iters = 150
+    note(f"case: matrix fp64 {case} unorm {unorm} wnorm {wnorm} {iters} it")
+    s, lam0, lam1, L = _solver(torch, case, alpha=0.8, tau=2.0, unorm=unorm, wnorm=wnorm)
+    info = s.solve(iters, 0.0, 50)
+    r = MO.solve_pair(lam0, lam1, L, alpha=0.8, tau=2.0, unorm=unorm, wnorm=wnorm, max_iters=iters, check_every=50)
+    st = s.get_state()
+    for key in ("phi", "ux", "uy", "w"):
+        a, b = _np(st[key]), r["state"][key]
+        scale = max(np.abs(b).max(), 1e-300)
+        assert np.abs(a - b).max() <= 1e-9 * scale, (key, np.abs(a - b).max(), scale)
+    M, inf = s.distance()
+    assert M == pytest.approx(r["primal"], rel=1e-10)
+    assert info["residual"] == pytest.approx(r["residual"], rel=1e-8)
+    assert inf["dual"] == pytest.approx(r["dual"], rel=1e-8, abs=1e-14)
+
+
+@pytest.mark.parametrize("case", ["dti_real_k3", "complex_k2"])
+def test_fp64_gradient_is_the_oracle_potential(case):
+    torch = cuda()
+    note(f"case: matrix gradient {case}")
+    s, lam0, lam1, L = _solver(torch, case, alpha=1.3, tau=1.0)
+    s.solve(400, 0.0, 64)
+    r = MO.solve_pair(lam0, lam1, L, alpha=1.3, tau=1.0, max_iters=400)
+    d0, d1 = s.grad()
+    assert torch.equal(d0, -d1)
+    g = _np(d0)
+    assert np.abs(g - r["Phi"]).max() <= 1e-9 * np.abs(r["Phi"]).max()
+    # Hermitian with zero total trace
+    assert np.allclose(g, np.conj(np.swapaxes(g, -1, -2)), atol=1e-14)
+    assert abs(np.trace(g.sum((0, 1)))) < 1e-9
+
+
+@pytest.mark.parametrize("comp", [False, True])
+def test_fp32_within_tolerance(comp):
+    torch = cuda()
+    note(f"case: matrix fp32 dti comp={comp}")
+    iters = 3000
+    s, lam0, lam1, L = _solver(torch, "dti_real_k3", f64=False, alpha=1.0, tau=2.0, compensated=comp)
+    s.solve(iters, 0.0, 64)
+    r = MO.solve_pair(lam0, lam1, L, alpha=1.0, tau=2.0, max_iters=iters)
+    M, _ = s.distance()
+    assert abs(M - r["primal"]) <= 1e-4 * r["primal"]
+    d0, _ = s.grad()
+    assert np.abs(_np(d0) - r["Phi"]).max() <= 1e-3
+
+
+def test_stopping_decision_matches_oracle():
+    torch = cuda()
+    note("case: matrix tol 3e-3 complex k2")
+    s, lam0, lam1, L = _solver(torch, "complex_k2", alpha=0.6, tau=1.0)
+    info = s.solve(100000, 3e-3, 32)
+    r = MO.solve_pair(lam0, lam1, L, alpha=0.6, tau=1.0, max_iters=100000, tol=3e-3, check_every=32)
+    assert info["converged"] and r["converged"]
+    assert info["iters"] == r["iters"]
+
+
+def test_matrix_error_paths():
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    m, n, k, real, L = CASES["dti_real_k3"]
+    lam0, lam1 = I.matrix_pair(9, m, n, k, real)
+    note("case: matrix EMASS")
+    with pytest.raises(omt.OMTError) as e:
+        omt.MatrixSolver(_dev(torch, lam0, True, True), _dev(torch, 1.5 * lam1, True, True), L)
+    assert e.value.status == omt.EMASS
+    note("case: matrix NaN")
+    bad = lam1.copy()
+    bad[3, 4, 0, 1] = np.nan
+    with pytest.raises(omt.OMTError) as e:
+        omt.MatrixSolver(_dev(torch, lam0, True, True), _dev(torch, bad, True, True), L)
+    assert e.value.status == omt.EINVAL
