@@ -38,9 +38,10 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations for the CPU baseline (0: auto)")
     ap.add_argument("--timing-launches", type=int, default=200)
-    ap.add_argument("--workload", default="large", choices=["large", "batched", "rgb", "loss"],
+    ap.add_argument("--workload", default="large", choices=["large", "batched", "rgb", "loss", "matrix"],
                     help="large: 1024x1024 k=8 throughput (default); batched: 96 pairs to 1e-5, batched vs "
-                         "plain; rgb: 256x256 k=3 time to 1e-5; loss: 8 pairs of 512x512 forward+backward")
+                         "plain; rgb: 256x256 k=3 time to 1e-5; loss: 8 pairs of 512x512 forward+backward; "
+                         "matrix: 3x3 matrix OMT, 256x256 time to a 1e-3 gap and 1024x1024 step roofline")
     ap.add_argument("--pairs", type=int, default=96, help="batched workload: number of pairs")
     ap.add_argument("--tol", type=float, default=0.0, help="time-to-tolerance workloads: tolerance (0: workload's)")
     ap.add_argument("--cap", type=int, default=3_000_000, help="time-to-tolerance workloads: iteration cap")
@@ -252,6 +253,52 @@ def bench_loss(a):
                          "parallelism": "single-gpu"}, V=[float(v) for v in V.detach().cpu()])
 
 
+def bench_matrix(a):
+    """Matrix OMT (Sec. 7.3) on diffusion-tensor-like real 3 x 3 fields with
+    the two matrices L_1, L_2 of the paper's example, ||U||_2 and ||W||_1:
+    time to |relative duality gap| <= 1e-3 on 256 x 256 with tau = 60 (the
+    precision measure, grid and tau of the paper's matrix table), and the
+    step kernel against the HBM roofline on 1024 x 1024."""
+    import torch
+    from paper_1712_10279_amd import inputs as I
+    from paper_1712_10279_amd import omt
+    gap = a.tol or 1e-3
+    dt, comp, label = _precision(a, "f32comp")
+    D = I.dti_like(256)
+    dev = lambda x: torch.as_tensor(x, dtype=dt, device="cuda")
+    s = omt.MatrixSolver(dev(D["lam0"]), dev(D["lam1"]), D["L"], alpha=1.0, tau=60.0, compensated=comp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, info = 0, None
+    while it < a.cap:
+        info = s.solve(1024, 0.0, 64)
+        it += 1024
+        # the gap of an iterate that is not yet feasible can have either sign
+        if abs(info["rel_gap"]) <= gap:
+            break
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    M01, _ = s.distance()
+    print(f"# matrix 256: {it} it, {el:.2f} s, M {M01:.6g}, gap {info['rel_gap']:.2e}", file=sys.stderr, flush=True)
+    # throughput of the step kernel on a 1024 x 1024 field
+    B = I.dti_like(1024)
+    s2 = omt.MatrixSolver(dev(B["lam0"]), dev(B["lam1"]), B["L"], alpha=1.0, tau=60.0, compensated=comp)
+    s2.solve(64, 0.0, 64)
+    us = s2.time_steps(0, a.timing_launches)
+    K, KW = 6, 6
+    per_px = (7 * K + 2 * KW) * (8 if dt == torch.float64 else 4) + (2 * K * 4 if comp else 0)
+    bytes_launch = per_px * 1024 * 1024
+    ach = bytes_launch / us / 1e3
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": None, "kernel": "pdhg_step_kernel (matrix kind, K=6 coordinates, 6 transfer coordinates)",
+            "bytes_per_launch": bytes_launch, "us_per_launch": us}
+    return _line("matrix OMT time to 1e-3 relative duality gap", el, "s", it, 0, el * 1e3 / it, dtype=_dtype_name(dt),
+                 config={"workload": "momt_256x256_real3x3_dti_L", "gap": gap, "tau": 60.0, "alpha": 1.0,
+                         "precision": label, "parallelism": "single-gpu"},
+                 roofline=roof, M=M01, rel_gap=info["rel_gap"], iterations=it,
+                 cell_iter_per_s=1024 * 1024 / (us * 1e-6))
+
+
 def main():
     a = _parse()
     if a.copy_calibration:
@@ -261,7 +308,7 @@ def main():
         if a.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus})", file=sys.stderr)
             sys.exit(2)
-        fn = {"batched": bench_batched, "rgb": bench_rgb, "loss": bench_loss}[a.workload]
+        fn = {"batched": bench_batched, "rgb": bench_rgb, "loss": bench_loss, "matrix": bench_matrix}[a.workload]
         print(json.dumps(fn(a)), flush=True)
         return
     if a.gpus != 1:

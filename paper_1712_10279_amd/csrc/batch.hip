@@ -215,7 +215,7 @@ template <typename R, bool COMP>
 __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_metrics_kernel(const BatchArgs ba, int var)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int t = blockIdx.x * STEP_WAVES_PER_WG + threadIdx.x / WAVE;
+    const int t = blockIdx.x * STEP_WAVES_PER_WG + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     if (t >= ba.total_mtiles) return;
     const int p = __builtin_amdgcn_readfirstlane(ba.mtile_pair[t]);
     if (ba.state[p].done) return;
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_decide_kernel(c
                                                                                  int last)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int p = blockIdx.x * STEP_WAVES_PER_WG + threadIdx.x / WAVE;
+    const int p = blockIdx.x * STEP_WAVES_PER_WG + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     if (p >= ba.B) return;
     BatchPairState &st = ba.state[p];
     if (st.done) return;

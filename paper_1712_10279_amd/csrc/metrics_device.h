@@ -44,15 +44,21 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
     constexpr int LA = L > 0 ? L : 1;
 #pragma unroll
     for (int q = 0; q < NMET; ++q) v[q] = 0.0;
+    // Tiles are 64-column aligned, so every lane's column is inside the
+    // padded pitch: all lanes load (unconditionally, from in-bounds
+    // addresses) and lanes past the grid add nothing.
     const int j = wc * WAVE + lane;
-    if (j >= a.n) return;
+    const bool jok = j < a.n;
     const int i0 = wr * MET_ROWS, i1 = min(i0 + MET_ROWS, a.m);
     const int64_t P = a.plane;
     const R *phi0 = a.phi_in, *phi1 = a.phi_out, *u0 = a.u_in, *u1 = a.u_out, *w0 = a.w_in, *w1 = a.w_out;
     const double inv_h = double(a.inv_h);
     for (int i = i0; i < i1; ++i) {
         const int64_t o = (int64_t)i * a.pitch + j;
-        const int64_t oi = o - a.pitch, oj = o - 1;
+        const int64_t oi = i > 0 ? o - a.pitch : o, oj = j > 0 ? o - 1 : o;
+        double acc[NMET];
+#pragma unroll
+        for (int q = 0; q < NMET; ++q) acc[q] = 0.0;
         double we0[LA], we1[LA];
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
@@ -70,14 +76,15 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
                 p1 += double(ld_field(&a.plo_out[c * P + o]));
             }
             const double dp = p1 - p0;
-            const double ux0 = i < a.m - 1 ? double(ld_field(&u0[c * P + o])) : 0.0;
-            const double ux1 = i < a.m - 1 ? double(ld_field(&u1[c * P + o])) : 0.0;
-            const double uy0 = j < a.n - 1 ? double(ld_field(&u0[(K + c) * P + o])) : 0.0;
-            const double uy1 = j < a.n - 1 ? double(ld_field(&u1[(K + c) * P + o])) : 0.0;
-            const double xl0 = i > 0 ? double(ld_field(&u0[c * P + oi])) : 0.0;
-            const double xl1 = i > 0 ? double(ld_field(&u1[c * P + oi])) : 0.0;
-            const double yl0 = j > 0 ? double(ld_field(&u0[(K + c) * P + oj])) : 0.0;
-            const double yl1 = j > 0 ? double(ld_field(&u1[(K + c) * P + oj])) : 0.0;
+            const double lx0 = double(ld_field(&u0[c * P + o])), lx1 = double(ld_field(&u1[c * P + o]));
+            const double ly0 = double(ld_field(&u0[(K + c) * P + o])), ly1 = double(ld_field(&u1[(K + c) * P + o]));
+            const double lxl0 = double(ld_field(&u0[c * P + oi])), lxl1 = double(ld_field(&u1[c * P + oi]));
+            const double lyl0 = double(ld_field(&u0[(K + c) * P + oj]));
+            const double lyl1 = double(ld_field(&u1[(K + c) * P + oj]));
+            const double ux0 = i < a.m - 1 ? lx0 : 0.0, ux1 = i < a.m - 1 ? lx1 : 0.0;
+            const double uy0 = j < a.n - 1 ? ly0 : 0.0, uy1 = j < a.n - 1 ? ly1 : 0.0;
+            const double xl0 = i > 0 ? lxl0 : 0.0, xl1 = i > 0 ? lxl1 : 0.0;
+            const double yl0 = j > 0 ? lyl0 : 0.0, yl1 = j > 0 ? lyl1 : 0.0;
             const double dux = ux1 - ux0, duy = uy1 - uy0;
             const double ddiv = ((dux - (xl1 - xl0)) + duy - (yl1 - yl0)) * inv_h;
             const double div1 = ((ux1 - xl1) + uy1 - yl1) * inv_h;
@@ -102,39 +109,42 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
                 }
             }
             const double fc = double(ld_field(&a.f[c * P + o]));
-            v[0] += dux * dux + duy * duy;
-            v[2] += dp * dp;
-            v[3] += dp * (ddiv - dgd);
-            v[5] += p1 * fc;
+            acc[0] += dux * dux + duy * duy;
+            acc[2] += dp * dp;
+            acc[3] += dp * (ddiv - dgd);
+            acc[5] += p1 * fc;
             const double r = (div1 - dg1) + fc;
-            v[6] += r * r;
-            v[7] += p1;
+            acc[6] += r * r;
+            acc[7] += p1;
             sq += ux1 * ux1 + uy1 * uy1;
             gx[c] = ux1;
             gy[c] = uy1;
             if (a.unorm == 0)
-                v[4] += sqrt(ux1 * ux1 + uy1 * uy1);
+                acc[4] += sqrt(ux1 * ux1 + uy1 * uy1);
             else if (a.unorm == 1)
-                v[4] += fabs(ux1) + fabs(uy1);
+                acc[4] += fabs(ux1) + fabs(uy1);
             else
                 u2 += ux1 * ux1 + uy1 * uy1;
         }
-        if (a.unorm == 2) v[4] += sqrt(u2);
+        if (a.unorm == 2) acc[4] += sqrt(u2);
         if constexpr (GK == G_MATRIX) {
-            if (a.unorm == 3) v[4] += group_norm<K>(a.uwt, gx) + group_norm<K>(a.uwt, gy);
+            if (a.unorm == 3) acc[4] += group_norm<K>(a.uwt, gx) + group_norm<K>(a.uwt, gy);
         }
         double wn = 0.0, w2 = 0.0;
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
-            v[1] += (we1[e] - we0[e]) * (we1[e] - we0[e]);
+            acc[1] += (we1[e] - we0[e]) * (we1[e] - we0[e]);
             wn += fabs(we1[e]);
             w2 += we1[e] * we1[e];
         }
         if (GK == G_MATRIX && a.wnorm == 2)
-            v[4] += a.alpha * group_norm<LA>(a.wwt, we1);
+            acc[4] += a.alpha * group_norm<LA>(a.wwt, we1);
         else
-            v[4] += a.alpha * (a.wnorm == 0 ? wn : sqrt(w2));
-        if (a.eps > 0.0) v[4] += a.eps * (sq + w2);  // quadratic regularisation
+            acc[4] += a.alpha * (a.wnorm == 0 ? wn : sqrt(w2));
+        if (a.eps > 0.0) acc[4] += a.eps * (sq + w2);  // quadratic regularisation
+        // lanes past the grid add nothing (their terms are dropped as a whole)
+#pragma unroll
+        for (int q = 0; q < NMET; ++q) v[q] += jok ? acc[q] : 0.0;
     }
 }
 

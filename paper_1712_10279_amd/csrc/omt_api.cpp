@@ -471,7 +471,9 @@ int default_rows(const omt_ctx *h, int T)
     if (h->r.rows > 0) return h->r.rows;
     if (h->tuned_rows > 0 && h->tuned_T == T) return h->tuned_rows;
     // just enough rows per wave that every wave of the launch is resident at
-    // once (one round over the chip), at least 2 rows and at most 32
+    // once (one round over the chip), at most 32: a wave's rows are a chain of
+    // dependent steps, so grids that fit the chip in one round take a single
+    // row per wave (shortest chain) despite its extra halo row
     StepLaunch Lc;
     Lc.dtype = h->r.dtype;
     Lc.k = h->r.k;
@@ -486,7 +488,7 @@ int default_rows(const omt_ctx *h, int T)
     const int64_t slots = int64_t(bpc) * cus * STEP_WAVES_PER_WG;
     const int64_t ncolw = (h->r.n + strip_cols(T) - 1) / strip_cols(T);
     int64_t rows = (h->r.m * ncolw + slots - 1) / slots;
-    rows = std::max<int64_t>(rows, 2);
+    rows = std::max<int64_t>(rows, 1);
     rows = std::min<int64_t>(rows, 32);
     return int(rows);
 }
@@ -1282,7 +1284,7 @@ namespace {
 // Rows per strip in the batched kernel: a strip's rows are a chain of
 // dependent steps, so small grids take short strips (their iterations are
 // latency-bound) and large grids 8 rows (fewer halo rows per strip).
-int batch_rows_default(int m) { return std::max(2, std::min(8, (m + 31) / 32)); }
+int batch_rows_default(int m) { return m <= 96 ? 1 : m <= 160 ? 2 : m <= 320 ? 4 : 8; }
 
 struct BatchLayout {
     std::vector<size_t> off, bytes;

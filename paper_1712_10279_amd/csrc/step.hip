@@ -53,7 +53,9 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void tile_metrics_kernel(c
                                                                                 int ntiles, double *partials)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int t = blockIdx.x * STEP_WAVES_PER_WG + threadIdx.x / WAVE;
+    // the tile index made provably wave-uniform, so the row bounds derived
+    // from it branch on the scalar unit
+    const int t = blockIdx.x * STEP_WAVES_PER_WG + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     if (t >= ntiles) return;
     double v[NMET];
     tile_metrics<R, K, GK, L, COMP>(a, t % ncolw, t / ncolw, lane, v);
