@@ -20,7 +20,6 @@
 namespace omt {
 namespace dev {
 
-constexpr int MET_ROWS = 16;
 
 // sum_g wt_g ||x_g||_2 of a grouped entry-wise norm (see group_scales)
 template <int N, typename W>
@@ -47,6 +46,7 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
     // Tiles are 64-column aligned, so every lane's column is inside the
     // padded pitch: all lanes load (unconditionally, from in-bounds
     // addresses) and lanes past the grid add nothing.
+    constexpr int MET_CH_UNROLL = (GK == G_MATRIX) ? K : 2;
     const int j = wc * WAVE + lane;
     const bool jok = j < a.n;
     const int i0 = wr * MET_ROWS, i1 = min(i0 + MET_ROWS, a.m);
@@ -68,7 +68,10 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
         }
         double u2 = 0.0, sq = 0.0;
         double gx[K], gy[K];  // u' of this pixel (grouped norm of the matrix kinds)
-#pragma unroll
+        // two channels at a time keep the live registers (and so the resident
+        // waves) in check; the matrix kinds index gx / gy by channel, so they
+        // unroll fully
+#pragma unroll MET_CH_UNROLL
         for (int c = 0; c < K; ++c) {
             double p0 = double(ld_field(&phi0[c * P + o])), p1 = double(ld_field(&phi1[c * P + o]));
             if (COMP) {
@@ -160,11 +163,21 @@ __device__ __forceinline__ double wave_sum(double x)
 // order (lane l takes tiles l, l+64, ...; then the wave tree).
 __device__ __forceinline__ void reduce_tiles(const double *partials, int t0, int nt, int lane, double *out)
 {
+    // all NMET sums advance together (one pass over the tiles, the loads of
+    // a tile's row independent of each other); each sum still adds its
+    // tiles in increasing order, so the result does not depend on this
+    double s[NMET];
+#pragma unroll
+    for (int q = 0; q < NMET; ++q) s[q] = 0.0;
+    for (int t = lane; t < nt; t += WAVE) {
+        const double *row = partials + (int64_t)(t0 + t) * NMET;
+#pragma unroll
+        for (int q = 0; q < NMET; ++q) s[q] += row[q];
+    }
+#pragma unroll
     for (int q = 0; q < NMET; ++q) {
-        double s = 0.0;
-        for (int t = lane; t < nt; t += WAVE) s += partials[(int64_t)(t0 + t) * NMET + q];
-        s = wave_sum(s);
-        if (lane == 0) out[q] = s;
+        const double v = wave_sum(s[q]);
+        if (lane == 0) out[q] = v;
     }
 }
 

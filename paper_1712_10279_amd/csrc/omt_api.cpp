@@ -364,7 +364,7 @@ Layout make_layout(const Resolved &r)
         o += r.comp ? pf * r.k : 0;
     }
     L.off_part = o;
-    const size_t met_tiles = size_t((r.n + WAVE - 1) / WAVE) * size_t((r.m + 15) / 16);
+    const size_t met_tiles = size_t((r.n + WAVE - 1) / WAVE) * size_t((r.m + MET_ROWS - 1) / MET_ROWS);
     size_t npart = std::max<size_t>(size_t(METRIC_BLOCKS_MAX) * KMAX, size_t(SUM_BLOCKS_MAX) * (4 * KMAX + 1));
     npart = std::max(npart, met_tiles * NMET);
     o += align256(sizeof(double) * npart);
@@ -539,7 +539,7 @@ omt_status run_metrics(omt_ctx *h, int old_c, int new_c, int old_w, int new_w, h
     if (!stream) stream = h->stream;
     const Resolved &r = h->r;
     const int ncolw = (r.n + WAVE - 1) / WAVE;
-    const int ntiles = ncolw * ((r.m + 15) / 16);
+    const int ntiles = ncolw * ((r.m + MET_ROWS - 1) / MET_ROWS);
     StepLaunch Lc;
     Lc.dtype = r.dtype;
     Lc.k = r.k;
@@ -1318,7 +1318,7 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
         const int ncolw = (r.n + WAVE - 1) / WAVE;
         L.rows.push_back(rows);
         L.ntiles.push_back(ncolw * ((r.m + rows - 1) / rows));
-        L.mtiles.push_back(ncolw * ((r.m + 15) / 16));
+        L.mtiles.push_back(ncolw * ((r.m + MET_ROWS - 1) / MET_ROWS));
         L.total_tiles += L.ntiles.back();
         L.total_mtiles += L.mtiles.back();
     }

@@ -13,6 +13,8 @@ constexpr int LMAX = 28;   // edges (complete graph on 8 nodes)
 constexpr int WAVE = 64;
 constexpr int STEP_WAVES_PER_WG = 4;
 constexpr int NMET = 8;  // su, sw, sp, cross, primal, dual, mass, sum_phi
+// rows of a check-iteration metrics tile (64 columns wide, one wave each)
+constexpr int MET_ROWS = 8;
 
 // Channel graphs the step kernel is compiled for.  The path (edges (c, c+1))
 // and the complete graph (all a < b in lexicographic order) get their
