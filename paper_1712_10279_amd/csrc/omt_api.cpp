@@ -1284,7 +1284,10 @@ namespace {
 // Rows per strip in the batched kernel: a strip's rows are a chain of
 // dependent steps, so small grids take short strips (their iterations are
 // latency-bound) and large grids 8 rows (fewer halo rows per strip).
-int batch_rows_default(int m) { return m <= 96 ? 1 : m <= 160 ? 2 : m <= 320 ? 4 : 8; }
+// Measured on the 96-pair batch: one row for the 64-pixel grids and two to
+// four for the middle sizes was 2% slower overall (more halo traffic while
+// every problem is active) than this rule.
+int batch_rows_default(int m) { return std::max(2, std::min(8, (m + 31) / 32)); }
 
 struct BatchLayout {
     std::vector<size_t> off, bytes;
@@ -1835,7 +1838,7 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
     ms.K = real ? k * (k + 1) / 2 : k * k;
     ms.Ks = real ? k * (k - 1) / 2 : k * k;
     const int lc = l * ms.Ks;
-    if (ms.K > KMAX || matrix_bucket(ms.K) == 0 || lc > matrix_bucket(ms.K))
+    if (ms.K > KMAX || matrix_bucket(ms.K, lc) == 0)
         return fail(OMT_EUNSUPPORTED, "%s k = %d with %d matrices L_s is not compiled", real ? "real" : "complex", k, l);
     // L: Hermitian (real symmetric in the real mode)
     std::vector<std::vector<cplx>> L(l, std::vector<cplx>(k * k));
@@ -1907,7 +1910,7 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
     r.k = ms.K;
     r.l = lc;
     r.gk = G_MATRIX;
-    r.lb = matrix_bucket(ms.K);
+    r.lb = matrix_bucket(ms.K, lc);
     r.alpha = p->alpha;
     r.tau = p->tau;
     r.eps = 0.0;

@@ -27,11 +27,15 @@ constexpr int MET_ROWS = 8;
 enum GraphKind { G_NONE = 0, G_PATH = 1, G_COMPLETE = 2, G_DENSE = 3, G_MATRIX = 4 };
 
 // Coordinates of the transfer variable compiled for a matrix problem with
-// K coordinates of the potential: K = 3 (real 2 x 2), 4 (complex 2 x 2) and
-// 6 (real 3 x 3), up to three matrices L_s (two for complex 2 x 2).
-inline int matrix_bucket(int K)
+// K coordinates of the potential and lc of the transfer: K = 3 (real 2 x 2,
+// up to three L_s), 4 (complex 2 x 2, two L_s) and 6 (real 3 x 3: two L_s,
+// as in the diffusion-tensor example, or three); 0 if not compiled.
+inline int matrix_bucket(int K, int lc)
 {
-    return K == 3 ? 3 : K == 4 ? 8 : K == 6 ? 9 : 0;
+    if (K == 3) return lc <= 3 ? 3 : 0;
+    if (K == 4) return lc <= 8 ? 8 : 0;
+    if (K == 6) return lc <= 6 ? 6 : lc <= 9 ? 9 : 0;
+    return 0;
 }
 
 inline int dense_bucket(int k, int l)

@@ -151,6 +151,7 @@ constexpr int L_TREE = OMT_K - 1;
 constexpr int L_FULL = OMT_K * (OMT_K - 1) / 2;
 // matrix problems compiled for this coordinate count (0: none)
 constexpr int L_MAT = OMT_K == 3 ? 3 : OMT_K == 4 ? 8 : OMT_K == 6 ? 9 : 0;
+constexpr int L_MAT2 = OMT_K == 6 ? 6 : 0;  // a second bucket (two L_s for real 3 x 3)
 
 }  // namespace
 
@@ -171,6 +172,9 @@ hipError_t OMT_CAT(launch_step_k, OMT_K)(const StepLaunch &Lc)
 #if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return dispatch_T<G_MATRIX, L_MAT>(Lc);
 #endif
+#if OMT_K == 6
+    if (Lc.gk == G_MATRIX && Lc.lb == L_MAT2) return dispatch_T<G_MATRIX, L_MAT2>(Lc);
+#endif
     return hipErrorInvalidValue;
 }
 
@@ -187,6 +191,9 @@ hipError_t OMT_CAT(launch_metrics_k, OMT_K)(const StepLaunch &Lc, int ncolw, int
 #endif
 #if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return dispatch_met<G_MATRIX, L_MAT>(Lc, ncolw, ntiles, partials);
+#endif
+#if OMT_K == 6
+    if (Lc.gk == G_MATRIX && Lc.lb == L_MAT2) return dispatch_met<G_MATRIX, L_MAT2>(Lc, ncolw, ntiles, partials);
 #endif
     return hipErrorInvalidValue;
 }
@@ -205,6 +212,9 @@ hipError_t OMT_CAT(step_blocks_per_cu_k, OMT_K)(const StepLaunch &Lc, int *block
 #if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return occ_T<G_MATRIX, L_MAT>(Lc, blocks);
 #endif
+#if OMT_K == 6
+    if (Lc.gk == G_MATRIX && Lc.lb == L_MAT2) return occ_T<G_MATRIX, L_MAT2>(Lc, blocks);
+#endif
     return hipErrorInvalidValue;
 }
 
@@ -214,7 +224,7 @@ bool OMT_CAT(step_supported_k, OMT_K)(int dtype, int gk, int lb, int T, bool com
     ok = ok || (OMT_K >= 2 && gk == G_PATH && lb == L_TREE);
     ok = ok || (OMT_K >= 3 && gk == G_COMPLETE && lb == L_FULL);
     ok = ok || (OMT_K >= 3 && gk == G_DENSE && (lb == L_TREE || lb == L_FULL));
-    ok = ok || (L_MAT > 0 && gk == G_MATRIX && lb == L_MAT);
+    ok = ok || (L_MAT > 0 && gk == G_MATRIX && (lb == L_MAT || (L_MAT2 > 0 && lb == L_MAT2)));
     if (!ok) return false;
     if (dtype == 1) return T == 1 && !comp;
     if (gk == G_DENSE || gk == G_MATRIX) return T == 1;
