@@ -193,6 +193,10 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
                                       R (&pOl)[K], R (&uxO)[K], R (&uyO)[K], R (&wO)[LA])
 {
     const int64_t P = a.plane;
+    // the matrix kinds only take the Frobenius (u 2, w 1) and grouped
+    // entry-wise (u 3, w 2) norms: fold the others away at compile time
+    const int unorm = (GK == G_MATRIX) ? (a.unorm == 3 ? 3 : 2) : a.unorm;
+    const int wnorm = (GK == G_MATRIX) ? (a.wnorm == 2 ? 2 : 1) : a.wnorm;
 
     // w-update: shrink_w(w + nu grad_G phi, alpha nu); (grad_G phi)_e =
     // (phi_a - phi_b) / c_e (Sec. 3.1), or M^T phi for a dense graph
@@ -217,16 +221,16 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
             }
         }
         if constexpr (GK == G_MATRIX) {
-            if (a.wnorm == 2) {
+            if (wnorm == 2) {
                 R sc[LA];
                 group_scales<R, LA>(a.wwt, wt, a.anu, sc);
 #pragma unroll
                 for (int e = 0; e < LA; ++e) wt[e] = wt[e] * sc[e];
             } else {
-                shrink_w<R, LA>(a.wnorm, wt, a.anu);
+                shrink_w<R, LA>(wnorm, wt, a.anu);
             }
         } else {
-            shrink_w<R, LA>(a.wnorm, wt, a.anu);
+            shrink_w<R, LA>(wnorm, wt, a.anu);
         }
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
@@ -270,7 +274,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
     };
     // ||u||_2 over all 2k components needs the norm of the whole block first
     R s_all = R(0), s_left = R(0);
-    if (a.unorm == 2) {
+    if (unorm == 2) {
         R r2 = R(0), r2l = R(0), tx, ty;
 #pragma unroll
         for (int c = 0; c < K; ++c) {
@@ -299,7 +303,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
 #pragma unroll
     for (int c = 0; c < K; ++c) gsx[c] = gsy[c] = gsxl[c] = gsyl[c] = R(0);
     if constexpr (GK == G_MATRIX) {
-        if (a.unorm == 3) {
+        if (unorm == 3) {
             R qx[K], qy[K];
 #pragma unroll
             for (int c = 0; c < K; ++c) utilde(c, qx[c], qy[c]);
@@ -314,11 +318,11 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         }
     }
     auto shrink_pair = [&](R tx, R ty, R sblock, R &bx, R &by) {
-        if (a.unorm == 0) {  // sum over channels of ||(u_x, u_y)||_2 (App. B shrink_2 per channel)
+        if (unorm == 0) {  // sum over channels of ||(u_x, u_y)||_2 (App. B shrink_2 per channel)
             const R s = shrink_scale<R>(sqrt(tx * tx + ty * ty), a.mu);
             bx = tx * s;
             by = ty * s;
-        } else if (a.unorm == 1) {  // element-wise shrink_1
+        } else if (unorm == 1) {  // element-wise shrink_1
             bx = tx * shrink_scale<R>(fabs(tx), a.mu);
             by = ty * shrink_scale<R>(fabs(ty), a.mu);
         } else {
@@ -332,7 +336,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
     for (int c = 0; c < K; ++c) {
         R tx, ty, bx, by;
         utilde(c, tx, ty);
-        if (GK == G_MATRIX && a.unorm == 3) {
+        if (GK == G_MATRIX && unorm == 3) {
             bx = tx * gsx[c];
             by = ty * gsy[c];
         } else {
@@ -347,7 +351,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         if (ALN) {
             R ex, ey, ebx, eby;
             utilde_left(c, ex, ey);
-            if (GK == G_MATRIX && a.unorm == 3) {
+            if (GK == G_MATRIX && unorm == 3) {
                 ebx = ex * gsxl[c];
                 eby = ey * gsyl[c];
             } else {

@@ -313,7 +313,30 @@ def _autograd_function():
             (d0,) = ctx.saved_tensors
             return g * d0, -g * d0, None, None, None, None, None
 
-    return OMTDistance
+    class OMTDistanceBatch(torch.autograd.Function):
+        """The same for a batch (B, m, n, k) of pairs solved together by the
+        batched solver (one launch per iteration for all unfinished pairs);
+        returns the (B,) distances."""
+
+        @staticmethod
+        def forward(ctx, rho0, rho1, edges, max_iters, tol, check_every, kw):
+            probs = [dict(rho0=rho0[b].detach(), rho1=rho1[b].detach(), edges=edges, **kw)
+                     for b in range(rho0.shape[0])]
+            bs = BatchSolver(probs)
+            ctx.infos = bs.solve(max_iters, tol, check_every)
+            V = bs.distance()
+            d0, _ = bs.grad()
+            d0 = torch.stack(d0)
+            ctx.save_for_backward(d0)
+            return torch.tensor(V, dtype=rho0.dtype, device=rho0.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            (d0,) = ctx.saved_tensors
+            gb = g.reshape(-1, 1, 1, 1)
+            return gb * d0, -gb * d0, None, None, None, None, None
+
+    return OMTDistance, OMTDistanceBatch
 
 
 _OMT_FN = None
@@ -325,11 +348,18 @@ def omt_loss(rho0, rho1, edges=None, max_iters=100000, tol=1e-6, check_every=64,
     global _OMT_FN
     if _OMT_FN is None:
         _OMT_FN = _autograd_function()
+    single, batched = _OMT_FN
     if rho0.dim() == 4:
         torch = _torch()
-        return torch.stack([_OMT_FN.apply(rho0[b], rho1[b], edges, max_iters, tol, check_every, kw)
+        try:
+            return batched.apply(rho0, rho1, edges, max_iters, tol, check_every, kw)
+        except OMTError as e:
+            if e.status != EUNSUPPORTED:
+                raise
+        # problems the batched kernel does not compile: one solve per pair
+        return torch.stack([single.apply(rho0[b], rho1[b], edges, max_iters, tol, check_every, kw)
                             for b in range(rho0.shape[0])])
-    return _OMT_FN.apply(rho0, rho1, edges, max_iters, tol, check_every, kw)
+    return single.apply(rho0, rho1, edges, max_iters, tol, check_every, kw)
 
 
 class BatchSolver:

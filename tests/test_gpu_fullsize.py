@@ -4,7 +4,8 @@ benchmark times, on sampled pixels the oracle can compute one by one.
 After N iterations a pixel depends only on the pixels within N of it, so the
 oracle runs on the crop of radius N+2 around each sample (with the full
 problem's f, h, mu and nu) and must agree with the GPU there.  FP32 samples
-are compared at the benchmark spec's tolerances scaled to the iterate size.
+are compared at the FP32 tolerances (1e-4 relative, 1e-3 absolute on the
+potential) scaled to the iterate size.
 """
 import numpy as np
 import pytest

@@ -74,9 +74,25 @@ def test_batched_loss_shapes():
     b = torch.stack([to_dev(torch, p[1], torch.float32) for p in pairs])
     V = omt.omt_loss(a, b, I.TRIANGLE, max_iters=500, tol=0.0)
     assert V.shape == (3,)
-    V.sum().backward()
+    wts = torch.tensor([1.0, -2.0, 0.5], device="cuda")
+    (V * wts).sum().backward()
     assert a.grad.shape == a.shape
     for q in range(3):
+        # the batched forward solves every pair exactly as its own solve does
         s = omt.Solver(a[q].detach(), b[q], I.TRIANGLE)
         s.solve(500, 0.0, 64)
-        assert torch.equal(s.grad()[0], a.grad[q])
+        assert float(V[q]) == float(torch.tensor(s.distance()[0], dtype=torch.float32))
+        assert torch.equal(wts[q] * s.grad()[0], a.grad[q])
+
+
+def test_batched_loss_falls_back_for_graphs_the_batch_does_not_compile():
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    pairs = [I.random_pair(80 + q, 10, 12, 5) for q in range(2)]
+    a = torch.stack([to_dev(torch, p[0], torch.float32) for p in pairs]).requires_grad_(True)
+    b = torch.stack([to_dev(torch, p[1], torch.float32) for p in pairs])
+    V = omt.omt_loss(a, b, I.path_edges(5), max_iters=200, tol=0.0)
+    V.sum().backward()
+    s = omt.Solver(a[1].detach(), b[1], I.path_edges(5))
+    s.solve(200, 0.0, 64)
+    assert torch.equal(s.grad()[0], a.grad[1])
