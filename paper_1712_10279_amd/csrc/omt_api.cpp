@@ -1194,7 +1194,7 @@ omt_status omt_autotune(omt_handle h, int32_t iters_per_trial, int32_t *best_t, 
     double bUs = 1e300, b1Us = 1e300;
     int b1R = 0;
     const int Ts[] = {1, 2, 4, 8};
-    const int Rs[] = {2, 3, 4, 6, 8, 12, 16, 24, 32};
+    const int Rs[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
     for (int T : Ts) {
         if (e != hipSuccess || st != OMT_OK) break;
         if (!step_supported(r.dtype, r.k, r.gk, r.lb, T, r.comp)) continue;
