@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "libomt.so")
 ARCH = os.environ.get("OMT_OFFLOAD_ARCH", "gfx950")
-KMAX = 8
+KMAX = 9
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 

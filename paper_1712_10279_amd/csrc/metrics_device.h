@@ -46,7 +46,7 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
     // Tiles are 64-column aligned, so every lane's column is inside the
     // padded pitch: all lanes load (unconditionally, from in-bounds
     // addresses) and lanes past the grid add nothing.
-    constexpr int MET_CH_UNROLL = (GK == G_MATRIX) ? K : 2;
+    constexpr int MET_CH_UNROLL = 2;
     const int j = wc * WAVE + lane;
     const bool jok = j < a.n;
     const int i0 = wr * MET_ROWS, i1 = min(i0 + MET_ROWS, a.m);
@@ -67,10 +67,12 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             we1[e] = on ? double(ld_field(&w1[e * P + o])) : 0.0;
         }
         double u2 = 0.0, sq = 0.0;
-        double gx[K], gy[K];  // u' of this pixel (grouped norm of the matrix kinds)
+        // grouped entry-wise norm of the matrix kinds, accumulated channel by
+        // channel: an open two-coordinate group keeps its first squares and
+        // its weight until its second coordinate arrives
+        double gpx = 0.0, gpy = 0.0, gw = 0.0;
         // two channels at a time keep the live registers (and so the resident
-        // waves) in check; the matrix kinds index gx / gy by channel, so they
-        // unroll fully
+        // waves) in check
 #pragma unroll MET_CH_UNROLL
         for (int c = 0; c < K; ++c) {
             double p0 = double(ld_field(&phi0[c * P + o])), p1 = double(ld_field(&phi1[c * P + o]));
@@ -120,8 +122,23 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             acc[6] += r * r;
             acc[7] += p1;
             sq += ux1 * ux1 + uy1 * uy1;
-            gx[c] = ux1;
-            gy[c] = uy1;
+            if constexpr (GK == G_MATRIX) {
+                if (a.unorm == 3) {
+                    const double wc = double(a.uwt[c]);
+                    if (wc > 0.0) {
+                        const bool pair = (c + 1 < K) && a.uwt[c + 1] == R(0);
+                        if (pair) {
+                            gpx = ux1 * ux1;
+                            gpy = uy1 * uy1;
+                            gw = wc;
+                        } else {
+                            acc[4] += wc * (fabs(ux1) + fabs(uy1));
+                        }
+                    } else {
+                        acc[4] += gw * (sqrt(gpx + ux1 * ux1) + sqrt(gpy + uy1 * uy1));
+                    }
+                }
+            }
             if (a.unorm == 0)
                 acc[4] += sqrt(ux1 * ux1 + uy1 * uy1);
             else if (a.unorm == 1)
@@ -130,9 +147,7 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
                 u2 += ux1 * ux1 + uy1 * uy1;
         }
         if (a.unorm == 2) acc[4] += sqrt(u2);
-        if constexpr (GK == G_MATRIX) {
-            if (a.unorm == 3) acc[4] += group_norm<K>(a.uwt, gx) + group_norm<K>(a.uwt, gy);
-        }
+
         double wn = 0.0, w2 = 0.0;
 #pragma unroll
         for (int e = 0; e < LA; ++e) {

@@ -32,6 +32,7 @@ hipError_t launch_step_k5(const StepLaunch &);
 hipError_t launch_step_k6(const StepLaunch &);
 hipError_t launch_step_k7(const StepLaunch &);
 hipError_t launch_step_k8(const StepLaunch &);
+hipError_t launch_step_k9(const StepLaunch &);
 hipError_t launch_metrics_k1(const StepLaunch &, int, int, double *);
 hipError_t launch_metrics_k2(const StepLaunch &, int, int, double *);
 hipError_t launch_metrics_k3(const StepLaunch &, int, int, double *);
@@ -40,6 +41,7 @@ hipError_t launch_metrics_k5(const StepLaunch &, int, int, double *);
 hipError_t launch_metrics_k6(const StepLaunch &, int, int, double *);
 hipError_t launch_metrics_k7(const StepLaunch &, int, int, double *);
 hipError_t launch_metrics_k8(const StepLaunch &, int, int, double *);
+hipError_t launch_metrics_k9(const StepLaunch &, int, int, double *);
 bool step_supported_k1(int, int, int, int, bool);
 bool step_supported_k2(int, int, int, int, bool);
 bool step_supported_k3(int, int, int, int, bool);
@@ -48,6 +50,7 @@ bool step_supported_k5(int, int, int, int, bool);
 bool step_supported_k6(int, int, int, int, bool);
 bool step_supported_k7(int, int, int, int, bool);
 bool step_supported_k8(int, int, int, int, bool);
+bool step_supported_k9(int, int, int, int, bool);
 
 hipError_t launch_step(const StepLaunch &L)
 {
@@ -60,6 +63,7 @@ hipError_t launch_step(const StepLaunch &L)
         case 6: return launch_step_k6(L);
         case 7: return launch_step_k7(L);
         case 8: return launch_step_k8(L);
+        case 9: return launch_step_k9(L);
         default: return hipErrorInvalidValue;
     }
 }
@@ -72,6 +76,7 @@ hipError_t step_blocks_per_cu_k5(const StepLaunch &, int *);
 hipError_t step_blocks_per_cu_k6(const StepLaunch &, int *);
 hipError_t step_blocks_per_cu_k7(const StepLaunch &, int *);
 hipError_t step_blocks_per_cu_k8(const StepLaunch &, int *);
+hipError_t step_blocks_per_cu_k9(const StepLaunch &, int *);
 
 hipError_t step_blocks_per_cu(const StepLaunch &L, int *blocks)
 {
@@ -84,6 +89,7 @@ hipError_t step_blocks_per_cu(const StepLaunch &L, int *blocks)
         case 6: return step_blocks_per_cu_k6(L, blocks);
         case 7: return step_blocks_per_cu_k7(L, blocks);
         case 8: return step_blocks_per_cu_k8(L, blocks);
+        case 9: return step_blocks_per_cu_k9(L, blocks);
         default: return hipErrorInvalidValue;
     }
 }
@@ -99,6 +105,7 @@ hipError_t launch_tile_metrics(const StepLaunch &L, int ncolw, int ntiles, doubl
         case 6: return launch_metrics_k6(L, ncolw, ntiles, partials);
         case 7: return launch_metrics_k7(L, ncolw, ntiles, partials);
         case 8: return launch_metrics_k8(L, ncolw, ntiles, partials);
+        case 9: return launch_metrics_k9(L, ncolw, ntiles, partials);
         default: return hipErrorInvalidValue;
     }
 }
@@ -114,6 +121,7 @@ bool step_supported(int dtype, int k, int gk, int lb, int T, bool comp)
         case 6: return step_supported_k6(dtype, gk, lb, T, comp);
         case 7: return step_supported_k7(dtype, gk, lb, T, comp);
         case 8: return step_supported_k8(dtype, gk, lb, T, comp);
+        case 9: return step_supported_k9(dtype, gk, lb, T, comp);
         default: return false;
     }
 }

@@ -8,7 +8,7 @@
 
 namespace omt {
 
-constexpr int KMAX = 8;    // channels
+constexpr int KMAX = 9;    // channels (8 for the vector method; 9 coordinates for complex 3 x 3 matrices)
 constexpr int LMAX = 28;   // edges (complete graph on 8 nodes)
 constexpr int WAVE = 64;
 constexpr int STEP_WAVES_PER_WG = 4;
@@ -28,13 +28,15 @@ enum GraphKind { G_NONE = 0, G_PATH = 1, G_COMPLETE = 2, G_DENSE = 3, G_MATRIX =
 
 // Coordinates of the transfer variable compiled for a matrix problem with
 // K coordinates of the potential and lc of the transfer: K = 3 (real 2 x 2,
-// up to three L_s), 4 (complex 2 x 2, two L_s) and 6 (real 3 x 3: two L_s,
-// as in the diffusion-tensor example, or three); 0 if not compiled.
+// up to three L_s), 4 (complex 2 x 2, two L_s), 6 (real 3 x 3: two L_s, as
+// in the diffusion-tensor example, or three) and 9 (complex 3 x 3, two
+// L_s); 0 if not compiled.
 inline int matrix_bucket(int K, int lc)
 {
     if (K == 3) return lc <= 3 ? 3 : 0;
     if (K == 4) return lc <= 8 ? 8 : 0;
     if (K == 6) return lc <= 6 ? 6 : lc <= 9 ? 9 : 0;
+    if (K == 9) return lc <= 18 ? 18 : 0;
     return 0;
 }
 

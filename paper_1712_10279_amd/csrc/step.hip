@@ -150,7 +150,7 @@ hipError_t dispatch_T(const StepLaunch &Lc)
 constexpr int L_TREE = OMT_K - 1;
 constexpr int L_FULL = OMT_K * (OMT_K - 1) / 2;
 // matrix problems compiled for this coordinate count (0: none)
-constexpr int L_MAT = OMT_K == 3 ? 3 : OMT_K == 4 ? 8 : OMT_K == 6 ? 9 : 0;
+constexpr int L_MAT = OMT_K == 3 ? 3 : OMT_K == 4 ? 8 : OMT_K == 6 ? 9 : OMT_K == 9 ? 18 : 0;
 constexpr int L_MAT2 = OMT_K == 6 ? 6 : 0;  // a second bucket (two L_s for real 3 x 3)
 
 }  // namespace
@@ -160,6 +160,7 @@ constexpr int L_MAT2 = OMT_K == 6 ? 6 : 0;  // a second bucket (two L_s for real
 
 hipError_t OMT_CAT(launch_step_k, OMT_K)(const StepLaunch &Lc)
 {
+#if OMT_K <= 8  // the vector method has at most 8 channels
     if (Lc.gk == G_NONE && Lc.lb == 0) return dispatch_T<G_NONE, 0>(Lc);
 #if OMT_K >= 2
     if (Lc.gk == G_PATH && Lc.lb == L_TREE) return dispatch_T<G_PATH, L_TREE>(Lc);
@@ -169,7 +170,8 @@ hipError_t OMT_CAT(launch_step_k, OMT_K)(const StepLaunch &Lc)
     if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return dispatch_T<G_DENSE, L_TREE>(Lc);
     if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return dispatch_T<G_DENSE, L_FULL>(Lc);
 #endif
-#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
+#endif
+#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6 || OMT_K == 9
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return dispatch_T<G_MATRIX, L_MAT>(Lc);
 #endif
 #if OMT_K == 6
@@ -180,6 +182,7 @@ hipError_t OMT_CAT(launch_step_k, OMT_K)(const StepLaunch &Lc)
 
 hipError_t OMT_CAT(launch_metrics_k, OMT_K)(const StepLaunch &Lc, int ncolw, int ntiles, double *partials)
 {
+#if OMT_K <= 8  // the vector method has at most 8 channels
     if (Lc.gk == G_NONE && Lc.lb == 0) return dispatch_met<G_NONE, 0>(Lc, ncolw, ntiles, partials);
 #if OMT_K >= 2
     if (Lc.gk == G_PATH && Lc.lb == L_TREE) return dispatch_met<G_PATH, L_TREE>(Lc, ncolw, ntiles, partials);
@@ -189,7 +192,8 @@ hipError_t OMT_CAT(launch_metrics_k, OMT_K)(const StepLaunch &Lc, int ncolw, int
     if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return dispatch_met<G_DENSE, L_TREE>(Lc, ncolw, ntiles, partials);
     if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return dispatch_met<G_DENSE, L_FULL>(Lc, ncolw, ntiles, partials);
 #endif
-#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
+#endif
+#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6 || OMT_K == 9
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return dispatch_met<G_MATRIX, L_MAT>(Lc, ncolw, ntiles, partials);
 #endif
 #if OMT_K == 6
@@ -200,6 +204,7 @@ hipError_t OMT_CAT(launch_metrics_k, OMT_K)(const StepLaunch &Lc, int ncolw, int
 
 hipError_t OMT_CAT(step_blocks_per_cu_k, OMT_K)(const StepLaunch &Lc, int *blocks)
 {
+#if OMT_K <= 8  // the vector method has at most 8 channels
     if (Lc.gk == G_NONE && Lc.lb == 0) return occ_T<G_NONE, 0>(Lc, blocks);
 #if OMT_K >= 2
     if (Lc.gk == G_PATH && Lc.lb == L_TREE) return occ_T<G_PATH, L_TREE>(Lc, blocks);
@@ -209,7 +214,8 @@ hipError_t OMT_CAT(step_blocks_per_cu_k, OMT_K)(const StepLaunch &Lc, int *block
     if (Lc.gk == G_DENSE && Lc.lb == L_TREE) return occ_T<G_DENSE, L_TREE>(Lc, blocks);
     if (Lc.gk == G_DENSE && Lc.lb == L_FULL) return occ_T<G_DENSE, L_FULL>(Lc, blocks);
 #endif
-#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
+#endif
+#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6 || OMT_K == 9
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return occ_T<G_MATRIX, L_MAT>(Lc, blocks);
 #endif
 #if OMT_K == 6
@@ -220,10 +226,10 @@ hipError_t OMT_CAT(step_blocks_per_cu_k, OMT_K)(const StepLaunch &Lc, int *block
 
 bool OMT_CAT(step_supported_k, OMT_K)(int dtype, int gk, int lb, int T, bool comp)
 {
-    bool ok = (gk == G_NONE && lb == 0);
-    ok = ok || (OMT_K >= 2 && gk == G_PATH && lb == L_TREE);
-    ok = ok || (OMT_K >= 3 && gk == G_COMPLETE && lb == L_FULL);
-    ok = ok || (OMT_K >= 3 && gk == G_DENSE && (lb == L_TREE || lb == L_FULL));
+    bool ok = (OMT_K <= 8 && gk == G_NONE && lb == 0);
+    ok = ok || (OMT_K >= 2 && OMT_K <= 8 && gk == G_PATH && lb == L_TREE);
+    ok = ok || (OMT_K >= 3 && OMT_K <= 8 && gk == G_COMPLETE && lb == L_FULL);
+    ok = ok || (OMT_K >= 3 && OMT_K <= 8 && gk == G_DENSE && (lb == L_TREE || lb == L_FULL));
     ok = ok || (L_MAT > 0 && gk == G_MATRIX && (lb == L_MAT || (L_MAT2 > 0 && lb == L_MAT2)));
     if (!ok) return false;
     if (dtype == 1) return T == 1 && !comp;

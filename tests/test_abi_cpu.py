@@ -107,6 +107,11 @@ def test_matrix_step_sizes_and_coordinates():
     L2 = np.stack([PAULI["x"], PAULI["z"]])
     _, _, _, lm2, K2, KW2 = omt.matrix_resolve(10, 10, L2, False)
     assert (K2, KW2) == (4, 8) and lm2 == pytest.approx(M.lambda_max(L2), rel=1e-12)
+    # complex 3 x 3 with two L_s: nine coordinates of Phi, eighteen of W
+    Lc = np.stack([PAULI["x"].real, PAULI["z"].real])
+    L3 = np.stack([np.array([[1, 1j, 0], [-1j, 0, 2], [0, 2, -1]]), np.diag([1.0, 0.0, -2.0]).astype(complex)])
+    _, _, _, lm4, K4, KW4 = omt.matrix_resolve(10, 10, L3, False)
+    assert (K4, KW4) == (9, 18) and lm4 == pytest.approx(M.lambda_max(L3), rel=1e-12)
     # a single L_s always commutes with itself, so the real 2 x 2 case takes two
     _, _, _, lm3, K3, KW3 = omt.matrix_resolve(10, 10, np.stack([PAULI["x"].real, PAULI["z"].real]), True)
     assert (K3, KW3) == (3, 2) and lm3 == pytest.approx(M.lambda_max(np.stack([PAULI["x"], PAULI["z"]])), rel=1e-12)

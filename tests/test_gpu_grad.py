@@ -81,7 +81,7 @@ def test_batched_loss_shapes():
         # the batched forward solves every pair exactly as its own solve does
         s = omt.Solver(a[q].detach(), b[q], I.TRIANGLE)
         s.solve(500, 0.0, 64)
-        assert float(V[q]) == float(torch.tensor(s.distance()[0], dtype=torch.float32))
+        assert float(V[q].detach()) == float(torch.tensor(s.distance()[0], dtype=torch.float32))
         assert torch.equal(wts[q] * s.grad()[0], a.grad[q])
 
 

@@ -25,6 +25,7 @@ CASES = {  # name: (m, n, k, real, L)
     "pauli_real_k2": (21, 130, 2, True, I.L_PAULI_XZ.real.copy()),
     "complex_k2": (33, 65, 2, False, np.stack([I.L_PAULI_XZ[0] + 0.3 * _herm(2), I.L_PAULI_XZ[1]])),
     "dti_plus_one_real_k3": (3, 130, 3, True, np.stack([I.L_DTI[0], I.L_DTI[1], np.diag([0.0, 1.0, -1.0])])),
+    "complex_k3": (20, 70, 3, False, np.stack([_herm(3), _herm(3)])),
 }
 
 
@@ -72,7 +73,7 @@ def test_fp64_state_matches_oracle(case, unorm, wnorm):
     assert inf["dual"] == pytest.approx(r["dual"], rel=1e-8, abs=1e-14)
 
 
-@pytest.mark.parametrize("case", ["dti_real_k3", "complex_k2"])
+@pytest.mark.parametrize("case", ["dti_real_k3", "complex_k2", "complex_k3"])
 def test_fp64_gradient_is_the_oracle_potential(case):
     torch = cuda()
     note(f"case: matrix gradient {case}")
