@@ -38,12 +38,12 @@ typedef struct omt_mctx *omt_matrix_handle;
 typedef enum {
     OMT_M_FRO = 0, /* ||.||_2: Frobenius norm of the whole block                  */
     OMT_M_L1 = 1,  /* ||.||_1: sum of the moduli of all entries                   */
-    OMT_M_NUC = 2  /* ||.||_{1,nuc}: sum of nuclear norms (not compiled: EUNSUPPORTED) */
+    OMT_M_NUC = 2  /* ||.||_{1,nuc}: sum of nuclear norms (not for complex 3 x 3)      */
 } omt_mnorm;
 
 typedef struct {
     int32_t m, n;       /* grid rows / columns, >= 2                               */
-    int32_t k;          /* matrix order: real mode k = 2 or 3, complex k = 2       */
+    int32_t k;          /* matrix order 2 or 3 (real or complex)                   */
     int32_t n_L;        /* l >= 1 matrices L_s (real k=2, k=3: <= 3; complex: <= 2) */
     const double *L;    /* host, l Hermitian k x k matrices, row-major, complex
                            entries as (re, im) pairs (l*k*k*2 doubles)              */

@@ -98,7 +98,7 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             if constexpr (L > 0) {
 #pragma unroll
                 for (int e = 0; e < LA; ++e) {
-                    if constexpr (GK == G_DENSE || GK == G_MATRIX) {
+                    if constexpr (GK == G_DENSE || is_matrix_kind(GK)) {
                         dgd += double(a.gm[c * LMAX + e]) * (we1[e] - we0[e]);
                         dg1 += double(a.gm[c * LMAX + e]) * we1[e];
                     } else {
@@ -122,7 +122,7 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             acc[6] += r * r;
             acc[7] += p1;
             sq += ux1 * ux1 + uy1 * uy1;
-            if constexpr (GK == G_MATRIX) {
+            if constexpr (is_matrix_kind(GK)) {
                 if (a.unorm == 3) {
                     const double wc = double(a.uwt[c]);
                     if (wc > 0.0) {
@@ -147,6 +147,18 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
                 u2 += ux1 * ux1 + uy1 * uy1;
         }
         if (a.unorm == 2) acc[4] += sqrt(u2);
+        if constexpr (GK == G_MATNUC) {
+            if (a.unorm == 4) {  // nuclear norm of each direction of u'
+                double cx[K], cy[K];
+#pragma unroll
+                for (int c = 0; c < K; ++c) {
+                    const double vx = double(ld_field(&u1[c * P + o])), vy = double(ld_field(&u1[(K + c) * P + o]));
+                    cx[c] = i < a.m - 1 ? vx : 0.0;
+                    cy[c] = j < a.n - 1 ? vy : 0.0;
+                }
+                acc[4] += herm_nuc<double, K>(cx) + herm_nuc<double, K>(cy);
+            }
+        }
 
         double wn = 0.0, w2 = 0.0;
 #pragma unroll
@@ -155,8 +167,10 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             wn += fabs(we1[e]);
             w2 += we1[e] * we1[e];
         }
-        if (GK == G_MATRIX && a.wnorm == 2)
+        if (is_matrix_kind(GK) && a.wnorm == 2)
             acc[4] += a.alpha * group_norm<LA>(a.wwt, we1);
+        else if (GK == G_MATNUC && a.wnorm == 3)
+            acc[4] += a.alpha * skew_nuc<K, LA>(we1, a.l);
         else
             acc[4] += a.alpha * (a.wnorm == 0 ? wn : sqrt(w2));
         if (a.eps > 0.0) acc[4] += a.eps * (sq + w2);  // quadratic regularisation

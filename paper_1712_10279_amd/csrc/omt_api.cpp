@@ -1834,8 +1834,7 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
         !std::isfinite(p->h))
         return fail(OMT_EINVAL, "mu, nu, h must be finite and >= 0");
     if (p->unorm < 0 || p->unorm > 2 || p->wnorm < 0 || p->wnorm > 2) return fail(OMT_EINVAL, "unknown norm");
-    if (p->unorm == OMT_M_NUC || p->wnorm == OMT_M_NUC)
-        return fail(OMT_EUNSUPPORTED, "nuclear norms are not compiled into the matrix kernels");
+
     if (p->dtype != OMT_F32 && p->dtype != OMT_F64) return fail(OMT_EINVAL, "unknown dtype %d", p->dtype);
     if (p->rows_per_wave < 0) return fail(OMT_EINVAL, "rows_per_wave must be >= 0");
     const int k = p->k, l = p->n_L;
@@ -1848,6 +1847,8 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
     const int lc = l * ms.Ks;
     if (ms.K > KMAX || matrix_bucket(ms.K, lc) == 0)
         return fail(OMT_EUNSUPPORTED, "%s k = %d with %d matrices L_s is not compiled", real ? "real" : "complex", k, l);
+    if ((p->unorm == OMT_M_NUC || p->wnorm == OMT_M_NUC) && ms.K == 9)
+        return fail(OMT_EUNSUPPORTED, "nuclear norms of complex 3 x 3 matrices are not compiled");
     // L: Hermitian (real symmetric in the real mode)
     std::vector<std::vector<cplx>> L(l, std::vector<cplx>(k * k));
     double big = 0.0;
@@ -1917,13 +1918,14 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
     r.n = p->n;
     r.k = ms.K;
     r.l = lc;
-    r.gk = G_MATRIX;
+    r.gk = (p->unorm == OMT_M_NUC || p->wnorm == OMT_M_NUC) ? G_MATNUC : G_MATRIX;
     r.lb = matrix_bucket(ms.K, lc);
     r.alpha = p->alpha;
     r.tau = p->tau;
     r.eps = 0.0;
-    r.unorm = p->unorm == OMT_M_FRO ? 2 : 3;
-    r.wnorm = p->wnorm == OMT_M_FRO ? 1 : 2;
+    // u norm 2 / 3 / 4 and w norm 1 / 2 / 3: Frobenius, grouped entry-wise, nuclear
+    r.unorm = p->unorm == OMT_M_FRO ? 2 : p->unorm == OMT_M_L1 ? 3 : 4;
+    r.wnorm = p->wnorm == OMT_M_FRO ? 1 : p->wnorm == OMT_M_L1 ? 2 : 3;
     r.dtype = p->dtype;
     r.comp = (p->flags & OMT_FLAG_COMPENSATED_PHI) && p->dtype == OMT_F32;
     r.tblock = 1;

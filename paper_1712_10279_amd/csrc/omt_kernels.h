@@ -24,7 +24,11 @@ constexpr int MET_ROWS = 8;
 // G_MATRIX: the matrix method in orthonormal real coordinates of the
 // Hermitian / skew-Hermitian matrices: a dense operator plus the grouped
 // entry-wise norms (u norm 3, w norm 2) of that coordinate system.
-enum GraphKind { G_NONE = 0, G_PATH = 1, G_COMPLETE = 2, G_DENSE = 3, G_MATRIX = 4 };
+// G_MATNUC: the same with the nuclear norms (u norm 4, w norm 3) compiled
+// in as well (their per-pixel eigendecompositions cost registers, so the
+// other matrix problems do not carry them).
+enum GraphKind { G_NONE = 0, G_PATH = 1, G_COMPLETE = 2, G_DENSE = 3, G_MATRIX = 4, G_MATNUC = 5 };
+constexpr bool is_matrix_kind(int gk) { return gk == G_MATRIX || gk == G_MATNUC; }
 
 // Coordinates of the transfer variable compiled for a matrix problem with
 // K coordinates of the potential and lc of the transfer: K = 3 (real 2 x 2,

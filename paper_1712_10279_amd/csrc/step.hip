@@ -87,7 +87,7 @@ hipError_t occ_T(const StepLaunch &Lc, int *blocks)
 {
     if (Lc.dtype == 1) return occ_one<double, GK, L, 1, false>(blocks);
     if (Lc.T == 1) return Lc.comp ? occ_one<float, GK, L, 1, true>(blocks) : occ_one<float, GK, L, 1, false>(blocks);
-    if constexpr (GK != G_DENSE && GK != G_MATRIX) {
+    if constexpr (GK != G_DENSE && !is_matrix_kind(GK)) {
         switch (Lc.T) {
             case 2: return Lc.comp ? occ_one<float, GK, L, 2, true>(blocks) : occ_one<float, GK, L, 2, false>(blocks);
 #if OMT_K <= 5
@@ -132,7 +132,7 @@ hipError_t dispatch_T(const StepLaunch &Lc)
         return hipErrorInvalidValue;
     }
     if (Lc.T == 1) return Lc.comp ? launch_one<float, GK, L, 1, true>(Lc) : launch_one<float, GK, L, 1, false>(Lc);
-    if constexpr (GK != G_DENSE && GK != G_MATRIX) {
+    if constexpr (GK != G_DENSE && !is_matrix_kind(GK)) {
         switch (Lc.T) {
             case 2: return Lc.comp ? launch_one<float, GK, L, 2, true>(Lc) : launch_one<float, GK, L, 2, false>(Lc);
 #if OMT_K <= 5
@@ -174,8 +174,12 @@ hipError_t OMT_CAT(launch_step_k, OMT_K)(const StepLaunch &Lc)
 #if OMT_K == 3 || OMT_K == 4 || OMT_K == 6 || OMT_K == 9
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return dispatch_T<G_MATRIX, L_MAT>(Lc);
 #endif
+#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
+    if (Lc.gk == G_MATNUC && Lc.lb == L_MAT) return dispatch_T<G_MATNUC, L_MAT>(Lc);
+#endif
 #if OMT_K == 6
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT2) return dispatch_T<G_MATRIX, L_MAT2>(Lc);
+    if (Lc.gk == G_MATNUC && Lc.lb == L_MAT2) return dispatch_T<G_MATNUC, L_MAT2>(Lc);
 #endif
     return hipErrorInvalidValue;
 }
@@ -196,8 +200,12 @@ hipError_t OMT_CAT(launch_metrics_k, OMT_K)(const StepLaunch &Lc, int ncolw, int
 #if OMT_K == 3 || OMT_K == 4 || OMT_K == 6 || OMT_K == 9
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return dispatch_met<G_MATRIX, L_MAT>(Lc, ncolw, ntiles, partials);
 #endif
+#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
+    if (Lc.gk == G_MATNUC && Lc.lb == L_MAT) return dispatch_met<G_MATNUC, L_MAT>(Lc, ncolw, ntiles, partials);
+#endif
 #if OMT_K == 6
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT2) return dispatch_met<G_MATRIX, L_MAT2>(Lc, ncolw, ntiles, partials);
+    if (Lc.gk == G_MATNUC && Lc.lb == L_MAT2) return dispatch_met<G_MATNUC, L_MAT2>(Lc, ncolw, ntiles, partials);
 #endif
     return hipErrorInvalidValue;
 }
@@ -218,8 +226,12 @@ hipError_t OMT_CAT(step_blocks_per_cu_k, OMT_K)(const StepLaunch &Lc, int *block
 #if OMT_K == 3 || OMT_K == 4 || OMT_K == 6 || OMT_K == 9
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT) return occ_T<G_MATRIX, L_MAT>(Lc, blocks);
 #endif
+#if OMT_K == 3 || OMT_K == 4 || OMT_K == 6
+    if (Lc.gk == G_MATNUC && Lc.lb == L_MAT) return occ_T<G_MATNUC, L_MAT>(Lc, blocks);
+#endif
 #if OMT_K == 6
     if (Lc.gk == G_MATRIX && Lc.lb == L_MAT2) return occ_T<G_MATRIX, L_MAT2>(Lc, blocks);
+    if (Lc.gk == G_MATNUC && Lc.lb == L_MAT2) return occ_T<G_MATNUC, L_MAT2>(Lc, blocks);
 #endif
     return hipErrorInvalidValue;
 }
@@ -231,9 +243,10 @@ bool OMT_CAT(step_supported_k, OMT_K)(int dtype, int gk, int lb, int T, bool com
     ok = ok || (OMT_K >= 3 && OMT_K <= 8 && gk == G_COMPLETE && lb == L_FULL);
     ok = ok || (OMT_K >= 3 && OMT_K <= 8 && gk == G_DENSE && (lb == L_TREE || lb == L_FULL));
     ok = ok || (L_MAT > 0 && gk == G_MATRIX && (lb == L_MAT || (L_MAT2 > 0 && lb == L_MAT2)));
+    ok = ok || (L_MAT > 0 && OMT_K != 9 && gk == G_MATNUC && (lb == L_MAT || (L_MAT2 > 0 && lb == L_MAT2)));
     if (!ok) return false;
     if (dtype == 1) return T == 1 && !comp;
-    if (gk == G_DENSE || gk == G_MATRIX) return T == 1;
+    if (gk == G_DENSE || is_matrix_kind(gk)) return T == 1;
     return t_ok(T);
 }
 

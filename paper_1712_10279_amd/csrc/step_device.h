@@ -147,6 +147,31 @@ __device__ __forceinline__ void group_scales(const R *wt, const R (&x)[N], R t, 
     }
 }
 
+}  // namespace dev
+}  // namespace omt
+
+#include "matrix_device.h"
+
+namespace omt {
+namespace dev {
+
+// Shrink of the u block of one direction of a matrix problem: the grouped
+// entry-wise norm (u norm 3) or the nuclear norm (u norm 4).
+template <typename R, int K, bool NUC>
+__device__ __forceinline__ void matrix_u_shrink(int unorm, const R *uwt, R (&x)[K], R t)
+{
+    if (!NUC || unorm == 3) {
+        R sc[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) sc[c] = R(0);
+        group_scales<R, K>(uwt, x, t, sc);
+#pragma unroll
+        for (int c = 0; c < K; ++c) x[c] = x[c] * sc[c];
+    } else {
+        herm_nuc_shrink<R, K>(x, t);
+    }
+}
+
 // ------------------------------------------------------------ channel graph
 
 // Endpoints (a_e, b_e), a_e < b_e, of edge e of the compiled graph kinds.
@@ -195,8 +220,10 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
     const int64_t P = a.plane;
     // the matrix kinds only take the Frobenius (u 2, w 1) and grouped
     // entry-wise (u 3, w 2) norms: fold the others away at compile time
-    const int unorm = (GK == G_MATRIX) ? (a.unorm == 3 ? 3 : 2) : a.unorm;
-    const int wnorm = (GK == G_MATRIX) ? (a.wnorm == 2 ? 2 : 1) : a.wnorm;
+    const int unorm = GK == G_MATNUC ? (a.unorm >= 3 ? a.unorm : 2) : GK == G_MATRIX ? (a.unorm == 3 ? 3 : 2)
+                                                                                     : a.unorm;
+    const int wnorm = GK == G_MATNUC ? (a.wnorm >= 2 ? a.wnorm : 1) : GK == G_MATRIX ? (a.wnorm == 2 ? 2 : 1)
+                                                                                     : a.wnorm;
 
     // w-update: shrink_w(w + nu grad_G phi, alpha nu); (grad_G phi)_e =
     // (phi_a - phi_b) / c_e (Sec. 3.1), or M^T phi for a dense graph
@@ -206,7 +233,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
             R s = R(0);
-            if constexpr (GK == G_DENSE || GK == G_MATRIX) {
+            if constexpr (GK == G_DENSE || is_matrix_kind(GK)) {
 #pragma unroll
                 for (int c = 0; c < K; ++c) {
                     s = s + a.gm[c * LMAX + e] * pA[c];
@@ -220,12 +247,14 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
                 wt[e] = w[e] + a.nu * (s * a.ic[e]);
             }
         }
-        if constexpr (GK == G_MATRIX) {
+        if constexpr (is_matrix_kind(GK)) {
             if (wnorm == 2) {
                 R sc[LA];
                 group_scales<R, LA>(a.wwt, wt, a.anu, sc);
 #pragma unroll
                 for (int e = 0; e < LA; ++e) wt[e] = wt[e] * sc[e];
+            } else if (GK == G_MATNUC && wnorm == 3) {
+                skew_nuc_shrink<R, K, LA>(wt, a.l, a.anu);
             } else {
                 shrink_w<R, LA>(wnorm, wt, a.anu);
             }
@@ -297,8 +326,9 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         s_all = shrink_scale<R>(sqrt(r2), a.mu);
         s_left = shrink_scale<R>(sqrt(r2l), a.mu);
     }
-    // grouped entry-wise norm of the matrix kinds: per-coordinate factors of
-    // this pixel and, in the aligned mode, of the pixel left of the strip
+    // grouped entry-wise norm of the matrix kinds (u norm 3): per-coordinate
+    // factors of this pixel and, in the aligned mode, of the pixel left of
+    // the strip
     R gsx[K], gsy[K], gsxl[K], gsyl[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) gsx[c] = gsy[c] = gsxl[c] = gsyl[c] = R(0);
@@ -314,6 +344,25 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
                 for (int c = 0; c < K; ++c) utilde_left(c, qx[c], qy[c]);
                 group_scales<R, K>(a.uwt, qx, a.mu, gsxl);
                 group_scales<R, K>(a.uwt, qy, a.mu, gsyl);
+            }
+        }
+    }
+    // the matrix kind with nuclear norms (u norm 3 or 4): the shrunk
+    // coordinates of each direction, as the shrink is no per-coordinate factor
+    R mx[K], my[K], mxl[K], myl[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) mx[c] = my[c] = mxl[c] = myl[c] = R(0);
+    if constexpr (GK == G_MATNUC) {
+        if (unorm >= 3) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) utilde(c, mx[c], my[c]);
+            matrix_u_shrink<R, K, true>(unorm, a.uwt, mx, a.mu);
+            matrix_u_shrink<R, K, true>(unorm, a.uwt, my, a.mu);
+            if (ALN) {
+#pragma unroll
+                for (int c = 0; c < K; ++c) utilde_left(c, mxl[c], myl[c]);
+                matrix_u_shrink<R, K, true>(unorm, a.uwt, mxl, a.mu);
+                matrix_u_shrink<R, K, true>(unorm, a.uwt, myl, a.mu);
             }
         }
     }
@@ -339,6 +388,9 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         if (GK == G_MATRIX && unorm == 3) {
             bx = tx * gsx[c];
             by = ty * gsy[c];
+        } else if (GK == G_MATNUC && unorm >= 3) {
+            bx = mx[c];
+            by = my[c];
         } else {
             shrink_pair(tx, ty, s_all, bx, by);
         }
@@ -354,6 +406,9 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
             if (GK == G_MATRIX && unorm == 3) {
                 ebx = ex * gsxl[c];
                 eby = ey * gsyl[c];
+            } else if (GK == G_MATNUC && unorm >= 3) {
+                ebx = mxl[c];
+                eby = myl[c];
             } else {
                 shrink_pair(ex, ey, s_left, ebx, eby);
             }
@@ -367,7 +422,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         if constexpr (L > 0) {
 #pragma unroll
             for (int e = 0; e < LA; ++e) {
-                if constexpr (GK == G_DENSE || GK == G_MATRIX) {
+                if constexpr (GK == G_DENSE || is_matrix_kind(GK)) {
                     dg = dg + a.gm[c * LMAX + e] * wb[e];
                 } else {
                     if (edge_a<GK, K>(e) == c) dg = dg + a.ic[e] * wb[e];

@@ -121,7 +121,8 @@ def test_matrix_step_sizes_and_coordinates():
     (PAULI["x"][None], False, {}, omt.EGRAPH),            # sigma_x commutes with itself: ker is span(I, sigma_x)
     (np.array([[[0, 1], [0, 0]]], complex), False, {}, omt.EINVAL),   # not Hermitian
     (PAULI["y"][None], True, {}, omt.EINVAL),             # imaginary L in the real mode
-    (L_DTI, True, {"unorm": omt.M_NUC}, omt.EUNSUPPORTED),
+    (np.stack([np.array([[1, 1j, 0], [-1j, 0, 2], [0, 2, -1]]), np.diag([1.0, 0.0, -2.0]).astype(complex)]), False,
+     {"unorm": omt.M_NUC}, omt.EUNSUPPORTED),           # nuclear norms of complex 3 x 3
     (np.stack([np.eye(3), np.diag([1.0, 2, 3])]), True, {}, omt.EGRAPH),  # commuting diagonals
     (np.stack([PAULI["x"], PAULI["z"], PAULI["y"]]), False, {}, omt.EUNSUPPORTED),  # 12 transfer coordinates
     (L_DTI, True, {"tau": 0.0}, omt.EINVAL),

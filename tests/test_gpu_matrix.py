@@ -73,6 +73,56 @@ def test_fp64_state_matches_oracle(case, unorm, wnorm):
     assert inf["dual"] == pytest.approx(r["dual"], rel=1e-8, abs=1e-14)
 
 
+# the oracle's nuclear shrinks diagonalise a 2k x 2k real image per matrix,
+# so these cases stay small
+NUC_CASES = {  # name: (m, n, k, real, L)
+    "dti_real_k3": (6, 70, 3, True, I.L_DTI),
+    "pauli_real_k2": (9, 66, 2, True, I.L_PAULI_XZ.real.copy()),
+    "complex_k2": (7, 65, 2, False, CASES["complex_k2"][4]),
+    "dti_plus_one_real_k3": (3, 66, 3, True, CASES["dti_plus_one_real_k3"][4]),
+}
+
+
+@pytest.mark.parametrize("case", list(NUC_CASES))
+@pytest.mark.parametrize("unorm,wnorm", [(MO.NUC, MO.NUC), (MO.FRO, MO.NUC), (MO.NUC, MO.L1)])
+def test_fp64_nuclear_norms_match_oracle(case, unorm, wnorm):
+    """Nuclear norms (per-pixel eigendecompositions on the GPU: closed form
+    for 2 x 2, Jacobi for real 3 x 3; the oracle diagonalises the real image
+    of each complex matrix)."""
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    m, n, k, real, L = NUC_CASES[case]
+    iters = 60
+    note(f"case: matrix fp64 nuclear {case} unorm {unorm} wnorm {wnorm} {iters} it")
+    lam0, lam1 = I.matrix_pair(6, m, n, k, real)
+    s = omt.MatrixSolver(_dev(torch, lam0, real, True), _dev(torch, lam1, real, True), L, alpha=0.8, tau=2.0,
+                         unorm=unorm, wnorm=wnorm)
+    info = s.solve(iters, 0.0, 30)
+    r = MO.solve_pair(lam0, lam1, L, alpha=0.8, tau=2.0, unorm=unorm, wnorm=wnorm, max_iters=iters, check_every=30)
+    st = s.get_state()
+    for key in ("phi", "ux", "uy", "w"):
+        a, b = _np(st[key]), r["state"][key]
+        assert np.abs(a - b).max() <= 1e-9 * max(np.abs(b).max(), 1e-300), key
+    M, _ = s.distance()
+    assert M == pytest.approx(r["primal"], rel=1e-10)
+    assert info["residual"] == pytest.approx(r["residual"], rel=1e-8)
+
+
+def test_fp32_nuclear_within_tolerance():
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    note("case: matrix fp32 nuclear dti 8x24, 500 it")
+    iters = 500
+    lam0, lam1 = I.matrix_pair(7, 8, 24, 3, True)
+    lam0, lam1 = lam0.astype(np.float32).astype(np.float64), lam1.astype(np.float32).astype(np.float64)
+    s = omt.MatrixSolver(_dev(torch, lam0, True, False), _dev(torch, lam1, True, False), I.L_DTI, alpha=1.0,
+                         tau=2.0, unorm=MO.NUC, wnorm=MO.NUC)
+    s.solve(iters, 0.0, 64)
+    r = MO.solve_pair(lam0, lam1, I.L_DTI, alpha=1.0, tau=2.0, unorm=MO.NUC, wnorm=MO.NUC, max_iters=iters)
+    M, _ = s.distance()
+    assert abs(M - r["primal"]) <= 1e-4 * r["primal"]
+
+
 @pytest.mark.parametrize("case", ["dti_real_k3", "complex_k2", "complex_k3"])
 def test_fp64_gradient_is_the_oracle_potential(case):
     torch = cuda()
