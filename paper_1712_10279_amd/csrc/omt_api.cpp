@@ -213,6 +213,17 @@ struct Resolved {
     std::vector<double> gmat, uwt, wwt;
 };
 
+// The step kernels reach all planes of a field (phi, u, w or f) from one
+// row through a buffer descriptor with 32-bit byte offsets: every field must
+// stay below 2 GiB.
+bool fields_fit(const Resolved &r)
+{
+    const int64_t pitch = (r.n + 63) / 64 * 64;
+    const int64_t planes = std::max(2 * r.k, std::max(r.lb, 1));
+    const int64_t esz = r.dtype == OMT_F64 ? 8 : 4;
+    return planes * r.m * pitch * esz < ((int64_t)1 << 31);
+}
+
 omt_status resolve(const omt_params *p, Resolved &r)
 {
     if (!p) return fail(OMT_EINVAL, "params is NULL");
@@ -327,6 +338,9 @@ omt_status resolve(const omt_params *p, Resolved &r)
         if (map[r.cls[c]] < 0) map[r.cls[c]] = r.ncls++;
         r.cls[c] = map[r.cls[c]];
     }
+    if (!fields_fit(r))
+        return fail(OMT_EUNSUPPORTED, "a field of %d x %d x %d %s values exceeds 2 GiB", r.m, r.n,
+                    std::max(2 * r.k, r.lb), r.dtype == OMT_F64 ? "FP64" : "FP32");
     return OMT_OK;
 }
 
@@ -1959,6 +1973,9 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
     r.cls.assign(ms.K, -1);
     for (int c = 0; c < nd; ++c) r.cls[c] = 0;
     r.ncls = 1;
+    if (!fields_fit(r))
+        return fail(OMT_EUNSUPPORTED, "a field of %d x %d x %d %s coordinates exceeds 2 GiB", r.m, r.n,
+                    std::max(2 * r.k, r.lb), r.dtype == OMT_F64 ? "FP64" : "FP32");
     return OMT_OK;
 }
 

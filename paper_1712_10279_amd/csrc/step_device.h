@@ -61,6 +61,55 @@ __device__ __forceinline__ void st_stream(R *p, R v)
         *gptr(p) = v;
 }
 
+// ------------------------------------------------------------ row buffers
+//
+// A strip reads and writes each plane one row at a time.  Every such access
+// goes through a raw buffer descriptor that spans exactly that row of that
+// plane (row_rsrc): the hardware range check returns 0 for a load and drops
+// a store whenever a lane's byte offset lies past the row, and a row that
+// must not be touched gets a descriptor of length 0.  Columns outside the
+// grid, lanes that must not store, and rows outside the strip's range thus
+// need no branch, so every memory instruction issues on every path and the
+// compiler can wait on exactly the loads it needs instead of on every store
+// still in flight.  The descriptor base and length are wave-uniform (SGPRs);
+// each lane's offset is fixed for the whole strip.
+constexpr int RSRC_WORD3 = 0x00020000;      // raw 32-bit data, gfx9-family buffer descriptor
+constexpr unsigned OFF_NONE = 0x80000000u;  // a byte offset past every row
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+// Descriptor from element `elem` (row r of plane 0) of a field whose planes
+// are P elements apart; plane c of that row is at byte offset c P s + j s.
+// `bytes` = ((planes - 1) P + n) s covers exactly the planes in use, and is
+// below 2^31 (checked by the host), so OFF_NONE + c P s stays past it.
+template <typename R>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const R *base, int64_t elem, bool valid, int bytes)
+{
+    // a zero-length descriptor never touches memory, whatever its base
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<R *>(base) + elem, (short)0, valid ? bytes : 0,
+                                             RSRC_WORD3);
+}
+// bytes a row descriptor of a field with `planes` planes must cover
+__device__ __forceinline__ int field_bytes(int planes, int64_t P, int n, int s)
+{
+    return int(((int64_t)(planes - 1) * P + n) * s);
+}
+template <typename R>
+__device__ __forceinline__ R buf_ld(__amdgpu_buffer_rsrc_t rs, unsigned off)
+{
+    if constexpr (sizeof(R) == 8)
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    else
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+template <typename R>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t rs, unsigned off, R v)
+{
+    if constexpr (sizeof(R) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, 0, 0);
+}
+
 // value of lane L (a wave-uniform result)
 __device__ __forceinline__ float lane_get(float v, int L)
 {
@@ -206,7 +255,10 @@ struct Edges {
 // Iteration of one pixel row r for this lane's column.  pA/pB: potential
 // on rows r and r+1 (hi and, if COMP, lo parts); ux, uy, w: state on row r;
 // carry: 2u'_x - u_x of row r-1 on entry, of row r on exit.  Outputs go to
-// pO/pOl/uxO/uyO/wO and, if st is set, straight to memory at offset o.  In
+// pO/pOl/uxO/uyO/wO and to memory: row r of each output plane (element
+// offset ro = r * pitch within the plane, planes P elements apart) if st_row
+// is set, at this lane's byte offset soff (OFF_NONE for a lane that must not
+// store).  In
 // the aligned mode (ALN) lane 63 takes its right potential and lane 0 its
 // left flux from E instead of the neighbouring lane; the left flux is
 // recomputed with the same expressions as every other pixel's.
@@ -214,10 +266,17 @@ template <typename R, int K, int GK, int L, int LA, bool COMP, bool ALN>
 __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_ok, bool last_row, bool last_col,
                                       const R (&pA)[K], const R (&pAl)[K], const R (&pB)[K], const R (&pBl)[K],
                                       const R (&ux)[K], const R (&uy)[K], const R (&w)[LA], const R (&f)[K],
-                                      const Edges<R> &E, bool st, int64_t o, R (&carry)[K], R (&pO)[K],
+                                      const Edges<R> &E, bool st_row, int64_t ro, unsigned soff, int64_t P,
+                                      R (&carry)[K], R (&pO)[K],
                                       R (&pOl)[K], R (&uxO)[K], R (&uyO)[K], R (&wO)[LA])
 {
-    const int64_t P = a.plane;
+    // this row of every output field (zero-length descriptors unless st_row)
+    const unsigned Psz = unsigned(P) * unsigned(sizeof(R)), Pszl = unsigned(P) * 4u;
+    const unsigned soffl = sizeof(R) == 4 ? soff : OFF_NONE;  // compensated potentials are FP32 only
+    const auto rphi = row_rsrc(a.phi_out, ro, st_row, field_bytes(K, P, a.n, sizeof(R)));
+    const auto ru = row_rsrc(a.u_out, ro, st_row, field_bytes(2 * K, P, a.n, sizeof(R)));
+    const auto rw = row_rsrc(a.w_out, ro, st_row && L > 0, field_bytes(a.l, P, a.n, sizeof(R)));
+    const auto rplo = row_rsrc(a.plo_out, ro, COMP && st_row, field_bytes(K, P, a.n, 4));
     // the matrix kinds only take the Frobenius (u 2, w 1) and grouped
     // entry-wise (u 3, w 2) norms: fold the others away at compile time
     const int unorm = GK == G_MATNUC ? (a.unorm >= 3 ? a.unorm : 2) : GK == G_MATRIX ? (a.unorm == 3 ? 3 : 2)
@@ -267,7 +326,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
             if (!lane_ok) wt[e] = R(0);
             wO[e] = wt[e];
             wb[e] = R(2) * wt[e] - w[e];
-            if (st && e < a.l) st_stream(&a.w_out[e * P + o], wt[e]);
+            if (L > 0) buf_st<R>(rw, soff + unsigned(e) * Psz, wt[e]);
         }
     }
 
@@ -448,12 +507,10 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         pOl[c] = pol;
         uxO[c] = bx;
         uyO[c] = by;
-        if (st) {
-            st_stream(&a.phi_out[c * P + o], po);
-            if (COMP) st_field(&a.plo_out[c * P + o], float(pol));
-            st_stream(&a.u_out[c * P + o], bx);
-            st_stream(&a.u_out[(K + c) * P + o], by);
-        }
+        buf_st<R>(rphi, soff + unsigned(c) * Psz, po);
+        if (COMP) buf_st<float>(rplo, soffl + unsigned(c) * Pszl, float(pol));
+        buf_st<R>(ru, soff + unsigned(c) * Psz, bx);
+        buf_st<R>(ru, soff + unsigned(K + c) * Psz, by);
     }
 }
 
@@ -475,11 +532,14 @@ __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int 
     constexpr int LA = L > 0 ? L : 1;
     constexpr bool ALN = (T == 1);  // aligned 64-column strips
 
+    // the strip's coordinates are wave-uniform: every row bound and buffer
+    // descriptor derived from them lives in scalar registers
+    wc = __builtin_amdgcn_readfirstlane(wc);
+    wr = __builtin_amdgcn_readfirstlane(wr);
     const int j = ALN ? wc * WAVE + lane : wc * (WAVE - 2 * T) - T + lane;
     const bool jin = (j >= 0) && (j < a.n);
     const bool jout = ALN ? jin : (jin && lane >= T && lane < WAVE - T);
     const bool last_col = (j == a.n - 1);
-    const int jc = jin ? j : 0;
     const int i0 = wr * a.rows;
     const int i1 = min(i0 + a.rows, a.m);
     const int rs = max(i0 - T, 0);
@@ -487,22 +547,34 @@ __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int 
     const int64_t P = a.plane;
     const int pitch = a.pitch;
 
-    const R *__restrict__ phi = a.phi_in + jc;
-    const float *__restrict__ plo = COMP ? a.plo_in + jc : nullptr;
-    const R *__restrict__ uin = a.u_in + jc;
-    const R *__restrict__ win = a.w_in + jc;
-    const R *__restrict__ fin = a.f + jc;
+    // this lane's byte offset in a row (past the row for a column outside
+    // the grid), and where it stores (only the strip's own columns)
+    const unsigned voff = jin ? unsigned(j) * unsigned(sizeof(R)) : OFF_NONE;
+    const unsigned voffl = jin ? unsigned(j) * 4u : OFF_NONE;  // compensated low parts (float)
+    const unsigned soff = jout ? voff : OFF_NONE;
+    const int nb_phi = field_bytes(K, P, a.n, sizeof(R)), nb_u = field_bytes(2 * K, P, a.n, sizeof(R));
+    const int nb_w = field_bytes(a.l, P, a.n, sizeof(R)), nb_lo = field_bytes(K, P, a.n, 4);
+
+    // plane stride in bytes, made opaque at every row step so that the
+    // compiler forms each plane's offset where it is used rather than
+    // keeping one per plane for the whole strip
+    unsigned Psz = unsigned(P) * unsigned(sizeof(R)), Pszl = unsigned(P) * 4u;
 
     // aligned mode: columns just outside the strip, lane c holding channel c
+    // (plane c of the field at that column; lanes >= K read nothing)
     const int jL = wc * WAVE - 1, jR = wc * WAVE + WAVE;
     const bool hasL = ALN && jL >= 0, hasR = ALN && jR < a.n;
     const bool hl = lane < K;
-    const int hc = hl ? lane : 0;
-    auto ld_edge = [&](int col, int r, const R *base, int plane0) -> R {
-        return ld_field(&base[(plane0 + hc) * P + (int64_t)r * pitch + col]);
+    const unsigned hcP = unsigned(hl ? lane : 0) * unsigned(P);
+    const unsigned eR = hl && hasR ? (hcP + unsigned(jR)) * unsigned(sizeof(R)) : OFF_NONE;
+    const unsigned eL = hl && hasL ? (hcP + unsigned(jL)) * unsigned(sizeof(R)) : OFF_NONE;
+    const unsigned eRl = hl && hasR ? (hcP + unsigned(jR)) * 4u : OFF_NONE;
+    const unsigned eLl = hl && hasL ? (hcP + unsigned(jL)) * 4u : OFF_NONE;
+    auto ld_edge = [&](unsigned eoff, int r, const R *base, int nb, int plane0, bool ok) -> R {
+        return buf_ld<R>(row_rsrc(base, (int64_t)r * pitch, ok, nb), eoff + unsigned(plane0) * Psz);
     };
-    auto ld_edge_lo = [&](int col, int r) -> R {
-        return R(ld_field(&a.plo_in[hc * P + (int64_t)r * pitch + col]));
+    auto ld_edge_lo = [&](unsigned eoff, int r, bool ok) -> R {
+        return R(buf_ld<float>(row_rsrc(a.plo_in, (int64_t)r * pitch, ok, nb_lo), eoff));
     };
     // next-row values (prefetched) of the edge columns
     R nRA = R(0), nRAl = R(0);                    // phi(r, jR)
@@ -511,45 +583,48 @@ __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int 
 
     // stage-0 inputs of the next row, loaded one step ahead
     R nA[K], nAl[K], nB[K], nBl[K], nux[K], nuy[K], nw[LA], nf[K];
-    auto load_phi = [&](int r, R (&hi)[K], R (&lo)[K]) {
+    // row r of the potential (ok: the row exists and is wanted)
+    auto load_phi = [&](int r, bool ok, R (&hi)[K], R (&lo)[K]) {
+        ok = ok && r < a.m;
+        const int64_t o = (int64_t)r * pitch;
+        const auto rp = row_rsrc(a.phi_in, o, ok, nb_phi);
+        const auto rl = row_rsrc(a.plo_in, o, COMP && ok, nb_lo);
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-            hi[c] = (jin && r < a.m) ? ld_field(&phi[c * P + (int64_t)r * pitch]) : R(0);
-            lo[c] = (COMP && jin && r < a.m) ? R(ld_field(&plo[c * P + (int64_t)r * pitch])) : R(0);
+            hi[c] = buf_ld<R>(rp, voff + unsigned(c) * Psz);
+            lo[c] = COMP ? R(buf_ld<float>(rl, voffl + unsigned(c) * Pszl)) : R(0);
         }
     };
-    // a single-iteration launch needs no w or f on its top halo row
-    auto load_rest = [&](int r) {
+    // row r of the fluxes, transfers and source; a single-iteration launch
+    // needs no w or f on its top halo row
+    auto load_rest = [&](int r, bool ok) {
         const int64_t o = (int64_t)r * pitch;
-        const bool full = !ALN || r >= i0;
+        const bool full = ok && (!ALN || r >= i0);
+        const auto ru = row_rsrc(a.u_in, o, ok, nb_u);
+        const auto rf = row_rsrc(a.f, o, full, nb_phi);
+        const auto rw = row_rsrc(a.w_in, o, L > 0 && full, nb_w);
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-            nux[c] = jin ? ld_stream(&uin[c * P + o]) : R(0);
-            nuy[c] = jin ? ld_stream(&uin[(K + c) * P + o]) : R(0);
-            nf[c] = (jin && full) ? ld_stream(&fin[c * P + o]) : R(0);
+            nux[c] = buf_ld<R>(ru, voff + unsigned(c) * Psz);
+            nuy[c] = buf_ld<R>(ru, voff + unsigned(K + c) * Psz);
+            nf[c] = buf_ld<R>(rf, voff + unsigned(c) * Psz);
         }
 #pragma unroll
-        for (int e = 0; e < LA; ++e) nw[e] = (L > 0 && jin && full && e < a.l) ? ld_stream(&win[e * P + o]) : R(0);
+        for (int e = 0; e < LA; ++e) nw[e] = (L > 0) ? buf_ld<R>(rw, voff + unsigned(e) * Psz) : R(0);
     };
     auto load_edges_first = [&](int r) {
-        if (hasR && hl) {
-            nRA = ld_edge(jR, r, a.phi_in, 0);
-            if (COMP) nRAl = ld_edge_lo(jR, r);
-        }
-        if (hasL && hl) {
-            nLA = ld_edge(jL, r, a.phi_in, 0);
-            if (COMP) nLAl = ld_edge_lo(jL, r);
-            if (r + 1 < a.m) {
-                nLB = ld_edge(jL, r + 1, a.phi_in, 0);
-                if (COMP) nLBl = ld_edge_lo(jL, r + 1);
-            }
-            nLux = ld_edge(jL, r, a.u_in, 0);
-            nLuy = ld_edge(jL, r, a.u_in, K);
-        }
+        nRA = ld_edge(eR, r, a.phi_in, nb_phi, 0, true);
+        if (COMP) nRAl = ld_edge_lo(eRl, r, true);
+        nLA = ld_edge(eL, r, a.phi_in, nb_phi, 0, true);
+        if (COMP) nLAl = ld_edge_lo(eLl, r, true);
+        nLB = ld_edge(eL, r + 1, a.phi_in, nb_phi, 0, r + 1 < a.m);
+        if (COMP) nLBl = ld_edge_lo(eLl, r + 1, r + 1 < a.m);
+        nLux = ld_edge(eL, r, a.u_in, nb_u, 0, true);
+        nLuy = ld_edge(eL, r, a.u_in, nb_u, K, true);
     };
-    load_phi(rs, nA, nAl);
-    load_phi(rs + 1, nB, nBl);
-    load_rest(rs);
+    load_phi(rs, true, nA, nAl);
+    load_phi(rs + 1, true, nB, nBl);
+    load_rest(rs, true);
     if (ALN) load_edges_first(rs);
 
     // pipeline registers: outputs of stage t on the previous (P) and the
@@ -573,6 +648,9 @@ __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int 
     const int nsteps = (re - rs) + T - 1;
     for (int s = 0; s < nsteps; ++s) {
         const int r0 = rs + s;
+        Psz = unsigned(P) * unsigned(sizeof(R));
+        Pszl = unsigned(P) * 4u;
+        asm volatile("" : "+s"(Psz), "+s"(Pszl));
         // current stage-0 inputs
         R cA[K], cAl[K], cB[K], cBl[K], cux[K], cuy[K], cw[LA];
 #pragma unroll
@@ -595,50 +673,46 @@ __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int 
         for (int c = 0; c < K; ++c) fq[0][c] = nf[c];
         const R cRA = nRA, cRAl = nRAl, cLA = nLA, cLAl = nLAl, cLB = nLB, cLBl = nLBl, cLux = nLux, cLuy = nLuy;
 
-        // prefetch the next row while this one is computed
-        if (r0 + 1 < re) {
+        // prefetch the next row while this one is computed: issued on every
+        // step (zero-length descriptors past the strip's last row), so that
+        // no path skips a memory instruction and the waits count exactly
+        const bool more = r0 + 1 < re;
 #pragma unroll
-            for (int c = 0; c < K; ++c) {
-                nA[c] = cB[c];
-                nAl[c] = cBl[c];
-            }
-            load_phi(r0 + 2, nB, nBl);
-            load_rest(r0 + 1);
-            if (ALN) {
-                if (hasR && hl) {
-                    nRA = ld_edge(jR, r0 + 1, a.phi_in, 0);
-                    if (COMP) nRAl = ld_edge_lo(jR, r0 + 1);
-                }
-                if (hasL && hl) {
-                    nLA = cLB;
-                    nLAl = cLBl;
-                    if (r0 + 2 < a.m) {
-                        nLB = ld_edge(jL, r0 + 2, a.phi_in, 0);
-                        if (COMP) nLBl = ld_edge_lo(jL, r0 + 2);
-                    }
-                    nLux = ld_edge(jL, r0 + 1, a.u_in, 0);
-                    nLuy = ld_edge(jL, r0 + 1, a.u_in, K);
-                }
-            }
+        for (int c = 0; c < K; ++c) {
+            nA[c] = cB[c];
+            nAl[c] = cBl[c];
+        }
+        load_phi(r0 + 2, more, nB, nBl);
+        load_rest(r0 + 1, more);
+        if (ALN) {
+            nRA = ld_edge(eR, r0 + 1, a.phi_in, nb_phi, 0, more);
+            if (COMP) nRAl = ld_edge_lo(eRl, r0 + 1, more);
+            nLA = cLB;
+            nLAl = cLBl;
+            nLB = ld_edge(eL, r0 + 2, a.phi_in, nb_phi, 0, more && r0 + 2 < a.m);
+            if (COMP) nLBl = ld_edge_lo(eLl, r0 + 2, more && r0 + 2 < a.m);
+            nLux = ld_edge(eL, r0 + 1, a.u_in, nb_u, 0, more);
+            nLuy = ld_edge(eL, r0 + 1, a.u_in, nb_u, K, more);
         }
 
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int r = r0 - t;
-            if (r >= rs && r < re) {
+            // one iteration per launch: every step is a row of the strip
+            if (T == 1 || (r >= rs && r < re)) {
                 const bool last_row = (r == a.m - 1);
-                const bool st = (t == T - 1) && jout && r >= i0 && r < i1;
-                const int64_t o = (int64_t)r * pitch + j;
+                const bool st_row = (t == T - 1) && r >= i0 && r < i1;
+                const int64_t ro = (int64_t)r * pitch;
                 if (t == 0) {
                     Edges<R> E{cRA, cRAl, cLA, cLAl, cLB, cLBl, cLux, cLuy, hasL};
                     stage<R, K, GK, L, LA, COMP, ALN>(a, lane, jin, last_row, last_col, cA, cAl, cB, cBl, cux, cuy,
-                                                      cw, fq[0], E, st, o, carry[0], phN[0], plN[0], uxN[0], uyN[0],
+                                                      cw, fq[0], E, st_row, ro, soff, P, carry[0], phN[0], plN[0], uxN[0], uyN[0],
                                                       wN[0]);
                 } else {
                     Edges<R> E{R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), false};
                     stage<R, K, GK, L, LA, COMP, false>(a, lane, jin, last_row, last_col, phP[t - 1], plP[t - 1],
                                                         phN[t - 1], plN[t - 1], uxP[t - 1], uyP[t - 1], wP[t - 1],
-                                                        fq[t], E, st, o, carry[t], phN[t], plN[t], uxN[t], uyN[t],
+                                                        fq[t], E, st_row, ro, soff, P, carry[t], phN[t], plN[t], uxN[t], uyN[t],
                                                         wN[t]);
                 }
             }

@@ -73,6 +73,14 @@ def test_size_limits():
     with pytest.raises(omt.OMTError) as e:
         omt.resolve_params(10, 10, 0, [])
     assert e.value.status == omt.EINVAL
+    # each field (here the 16 flux planes) must stay below 2 GiB: 32-bit
+    # byte offsets inside the kernels' row buffers
+    path8 = [(c, c + 1) for c in range(7)]
+    omt.resolve_params(5760, 5760, 8, path8)
+    for m, n, dt in ((5824, 5824, "f32"), (5760, 5760, "f64")):
+        with pytest.raises(omt.OMTError) as e:
+            omt.resolve_params(m, n, 8, path8, dtype=dt)
+        assert e.value.status == omt.EUNSUPPORTED
 
 
 def test_workspace_size_grows_with_problem():
