@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1455,6 +1456,7 @@ omt_status batch_solve_graphs(omt_bctx *h, BatchArgs ba, int64_t max_iters, int 
     int nchecks = 0;
     unsigned stopped = 0;
     const bool verbose = std::getenv("OMT_VERBOSE") != nullptr;
+    auto last_note = std::chrono::steady_clock::now();
     while (done < max_iters && stopped < unsigned(h->B)) {
         const int64_t nblk = std::min<int64_t>(K, max_iters - done);
         const bool last = done + nblk == max_iters;
@@ -1498,9 +1500,15 @@ omt_status batch_solve_graphs(omt_bctx *h, BatchArgs ba, int64_t max_iters, int 
         ++nchecks;
         HIP_TRY(hipMemcpyAsync(h->host_stopped, h->d_bar + 3, sizeof(unsigned), hipMemcpyDeviceToHost, h->cap));
         HIP_TRY(hipStreamSynchronize(h->cap));
-        if (verbose && *h->host_stopped != stopped)
-            std::fprintf(stderr, "omt batch: %u of %d problems stopped after %lld iterations\n", *h->host_stopped,
-                         h->B, (long long)done);
+        if (verbose) {
+            // a line when problems stop, and at least every 20 s otherwise
+            const auto now = std::chrono::steady_clock::now();
+            if (*h->host_stopped != stopped || now - last_note > std::chrono::seconds(20)) {
+                std::fprintf(stderr, "omt batch: %u of %d problems stopped after %lld iterations\n",
+                             *h->host_stopped, h->B, (long long)done);
+                last_note = now;
+            }
+        }
         const bool more = *h->host_stopped != stopped;
         stopped = *h->host_stopped;
         if (more && stopped < unsigned(h->B) && done < max_iters) {
