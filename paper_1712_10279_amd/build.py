@@ -82,7 +82,7 @@ if __name__ == "__main__":
     import time
     ap = argparse.ArgumentParser()
     ap.add_argument("-v", action="store_true")
-    ap.add_argument("-D", action="append", default=[], help="extra macro, e.g. -D OMT_STREAM_NT=1")
+    ap.add_argument("-D", action="append", default=[], help="extra preprocessor macro NAME=VALUE (variant builds side by side)")
     ap.add_argument("-o", default=None, help="library path (default: the package's libomt.so)")
     args = ap.parse_args()
     t0 = time.time()

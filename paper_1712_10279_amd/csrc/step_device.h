@@ -14,65 +14,36 @@ __device__ __forceinline__ float lane_prev(float v) { return __shfl_up(v, 1u, WA
 __device__ __forceinline__ double lane_next(double v) { return __shfl_down(v, 1u, WAVE); }
 __device__ __forceinline__ double lane_prev(double v) { return __shfl_up(v, 1u, WAVE); }
 
-// Streamed fields (u, w, f read once per pass; all outputs written once) may
-// carry the non-temporal hint so that they do not displace the potential
-// rows that neighbouring waves still read.  Off unless OMT_STREAM_NT is set.
-#ifndef OMT_STREAM_NT
-#define OMT_STREAM_NT 0
-#endif
-//
-// Every field access goes through a global-address-space pointer.  The
-// batched kernel reads its field pointers from a table in memory, where the
-// compiler cannot infer the address space and would otherwise emit flat
-// accesses, which wait on both the vector-memory and the LDS counters.
+// Field accesses outside the step's row buffers (the metrics kernel) go
+// through a global-address-space pointer.  The batched kernels read their
+// field pointers from a table in memory, where the compiler cannot infer the
+// address space and would otherwise emit flat accesses, which wait on both
+// the vector-memory and the LDS counters.
 #define OMT_GLOBAL __attribute__((address_space(1)))
 template <typename T>
 __device__ __forceinline__ const OMT_GLOBAL T *gptr(const T *p)
 {
     return (const OMT_GLOBAL T *)p;
 }
-template <typename T>
-__device__ __forceinline__ OMT_GLOBAL T *gptr(T *p)
-{
-    return (OMT_GLOBAL T *)p;
-}
 template <typename R>
 __device__ __forceinline__ R ld_field(const R *p)
 {
     return *gptr(p);
 }
-template <typename R>
-__device__ __forceinline__ void st_field(R *p, R v)
-{
-    *gptr(p) = v;
-}
-template <typename R>
-__device__ __forceinline__ R ld_stream(const R *p)
-{
-    if constexpr (OMT_STREAM_NT != 0) return __builtin_nontemporal_load(gptr(p));
-    return *gptr(p);
-}
-template <typename R>
-__device__ __forceinline__ void st_stream(R *p, R v)
-{
-    if constexpr (OMT_STREAM_NT != 0)
-        __builtin_nontemporal_store(v, gptr(p));
-    else
-        *gptr(p) = v;
-}
 
 // ------------------------------------------------------------ row buffers
 //
-// A strip reads and writes each plane one row at a time.  Every such access
-// goes through a raw buffer descriptor that spans exactly that row of that
-// plane (row_rsrc): the hardware range check returns 0 for a load and drops
-// a store whenever a lane's byte offset lies past the row, and a row that
-// must not be touched gets a descriptor of length 0.  Columns outside the
-// grid, lanes that must not store, and rows outside the strip's range thus
-// need no branch, so every memory instruction issues on every path and the
+// A strip reads and writes each field (all planes of phi, u, w, f) one row
+// at a time.  Every such access goes through a raw buffer descriptor that
+// starts at that row of the field's first plane and covers the field's
+// planes in use (row_rsrc); a lane reaches plane c, column j at byte offset
+// (c P + j) s.  The hardware range check returns 0 for a load and drops a
+// store whenever that offset lies past the descriptor: a lane outside the
+// grid, or one that must not store, carries offset OFF_NONE, and a row that
+// must not be touched gets a descriptor of length 0.  So no memory
+// instruction needs a branch, every one issues on every path, and the
 // compiler can wait on exactly the loads it needs instead of on every store
-// still in flight.  The descriptor base and length are wave-uniform (SGPRs);
-// each lane's offset is fixed for the whole strip.
+// still in flight.  Descriptors are wave-uniform (scalar registers).
 constexpr int RSRC_WORD3 = 0x00020000;      // raw 32-bit data, gfx9-family buffer descriptor
 constexpr unsigned OFF_NONE = 0x80000000u;  // a byte offset past every row
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
