@@ -214,15 +214,30 @@ struct Resolved {
     std::vector<double> gmat, uwt, wwt;
 };
 
+// Planes of a field lie one plane stride apart: m rows of the 64-aligned
+// pitch, plus a skew of 4 KiB + 256 B.  Without it, planes of a power-of-two
+// size (256^2, 512^2, 1024^2 FP32) put the same pixel of every plane on the
+// same HBM channel and bank, and a strip's dozens of concurrent plane
+// streams collide: a streaming probe of 36 read and 31 write planes of
+// 1024^2 floats moved 5.0 TB/s unskewed and 6.0 TB/s with this skew.
+#ifndef OMT_PLANE_SKEW_BYTES
+#define OMT_PLANE_SKEW_BYTES (4096 + 256)
+#endif
+constexpr int64_t PLANE_SKEW_BYTES = OMT_PLANE_SKEW_BYTES;
+static_assert(PLANE_SKEW_BYTES % 256 == 0, "planes stay 256-byte aligned");
+
+int row_pitch(int n) { return (n + 63) / 64 * 64; }
+
+int64_t plane_elems(int m, int n, int esz) { return (int64_t)m * row_pitch(n) + PLANE_SKEW_BYTES / esz; }
+
 // The step kernels reach all planes of a field (phi, u, w or f) from one
 // row through a buffer descriptor with 32-bit byte offsets: every field must
 // stay below 2 GiB.
 bool fields_fit(const Resolved &r)
 {
-    const int64_t pitch = (r.n + 63) / 64 * 64;
     const int64_t planes = std::max(2 * r.k, std::max(r.lb, 1));
-    const int64_t esz = r.dtype == OMT_F64 ? 8 : 4;
-    return planes * r.m * pitch * esz < ((int64_t)1 << 31);
+    const int esz = r.dtype == OMT_F64 ? 8 : 4;
+    return planes * plane_elems(r.m, r.n, esz) * esz < ((int64_t)1 << 31);
 }
 
 omt_status resolve(const omt_params *p, Resolved &r)
@@ -363,8 +378,8 @@ Layout make_layout(const Resolved &r)
 {
     Layout L;
     L.esz = r.dtype == OMT_F64 ? 8 : 4;
-    L.pitch = (r.n + 63) / 64 * 64;
-    L.plane = (int64_t)r.m * L.pitch;
+    L.pitch = row_pitch(r.n);
+    L.plane = plane_elems(r.m, r.n, int(L.esz));
     const size_t pb = align256(size_t(L.plane) * L.esz);
     size_t o = 0;
     L.off_f = o;
@@ -496,7 +511,10 @@ int default_rows(const omt_ctx *h, int T)
     // just enough rows per wave that every wave of the launch is resident at
     // once (one round over the chip), at most 32: a wave's rows are a chain of
     // dependent steps, so grids that fit the chip in one round take a single
-    // row per wave (shortest chain) despite its extra halo row
+    // row per wave (shortest chain) despite its extra halo row.  The round
+    // counts at most two waves per SIMD even where three fit: two already
+    // keep HBM busy, and the taller strips read fewer halo rows (1024^2 at
+    // k = 8: 8 rows at two waves per SIMD 55.7 us, 6 rows at three 57.0 us)
     StepLaunch Lc;
     Lc.dtype = h->r.dtype;
     Lc.k = h->r.k;
@@ -508,7 +526,7 @@ int default_rows(const omt_ctx *h, int T)
     if (step_blocks_per_cu(Lc, &bpc) != hipSuccess || bpc < 1) bpc = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus < 1)
         cus = 256;
-    const int64_t slots = int64_t(bpc) * cus * STEP_WAVES_PER_WG;
+    const int64_t slots = std::min<int64_t>(int64_t(bpc) * STEP_WAVES_PER_WG, 2 * 4) * cus;
     const int64_t ncolw = (h->r.n + strip_cols(T) - 1) / strip_cols(T);
     int64_t rows = (h->r.m * ncolw + slots - 1) / slots;
     rows = std::max<int64_t>(rows, 1);
