@@ -126,9 +126,10 @@ void omt_params_init(omt_params *p);
  * spacing and step sizes and lambda_max(-Delta_G) (Sec. 7.2).  Any output
  * pointer may be NULL.  Size limit: the kernels address each field (the k
  * potential planes, the 2k flux planes, the transfer planes) with 32-bit
- * byte offsets, so max(2k, edges compiled) x m x ceil64(n) x (4 or 8 bytes)
- * must stay below 2 GiB (OMT_EUNSUPPORTED otherwise; at k = 8 in FP32 the
- * largest square grid is 5760 x 5760). */
+ * byte offsets, so max(2k, edges compiled) planes of m x ceil64(n) values
+ * (4 or 8 bytes each, plus 4352 bytes of skew per plane) must stay below
+ * 2 GiB (OMT_EUNSUPPORTED otherwise; at k = 8 in FP32 the largest square
+ * grid is 5760 x 5760). */
 omt_status omt_resolve_params(const omt_params *p, double *h, double *mu, double *nu, double *lambda_max);
 
 /* Host only.  Bytes of device workspace omt_create needs for *p. */
