@@ -55,9 +55,10 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 template <typename R>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const R *base, int64_t elem, bool valid, int bytes)
 {
-    // a zero-length descriptor never touches memory, whatever its base
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<R *>(base) + elem, (short)0, valid ? bytes : 0,
-                                             RSRC_WORD3);
+    // a zero-length descriptor never touches memory; its base stays at the
+    // field's start so that no pointer past the allocation is formed
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<R *>(base) + (valid ? elem : 0), (short)0,
+                                             valid ? bytes : 0, RSRC_WORD3);
 }
 // bytes a row descriptor of a field with `planes` planes must cover
 __device__ __forceinline__ int field_bytes(int planes, int64_t P, int n, int s)
