@@ -504,10 +504,17 @@ void fill_args(StepArgs<R> &a, const omt_ctx *h, int ci, int co, int wi, int wo,
 // launch, 64 - 2T (plus halo lanes) when T iterations are pipelined.
 int strip_cols(int T) { return T == 1 ? WAVE : WAVE - 2 * T; }
 
+int rule_rows(const omt_ctx *h, int T);
+
 int default_rows(const omt_ctx *h, int T)
 {
     if (h->r.rows > 0) return h->r.rows;
     if (h->tuned_rows > 0 && h->tuned_T == T) return h->tuned_rows;
+    return rule_rows(h, T);
+}
+
+int rule_rows(const omt_ctx *h, int T)
+{
     // just enough rows per wave that every wave of the launch is resident at
     // once (one round over the chip), at most 32: a wave's rows are a chain of
     // dependent steps, so grids that fit the chip in one round take a single
@@ -528,10 +535,12 @@ int default_rows(const omt_ctx *h, int T)
         cus = 256;
     const int64_t slots = std::min<int64_t>(int64_t(bpc) * STEP_WAVES_PER_WG, 2 * 4) * cus;
     const int64_t ncolw = (h->r.n + strip_cols(T) - 1) / strip_cols(T);
-    int64_t rows = (h->r.m * ncolw + slots - 1) / slots;
-    rows = std::max<int64_t>(rows, 1);
-    rows = std::min<int64_t>(rows, 32);
-    return int(rows);
+    // the fewest rows whose strips, ceil(m / rows) per column block, all fit
+    // in one round (T = 2 at 1024^2 k = 8: 9 rows would need 2,052 waves
+    // for 2,048 slots, and the 4 left over take a whole second round)
+    int64_t rows = std::max<int64_t>(1, (h->r.m * ncolw + slots - 1) / slots);
+    while (rows < 32 && (h->r.m + rows - 1) / rows * ncolw > slots) ++rows;
+    return int(std::min<int64_t>(rows, 32));
 }
 
 // One launch advancing T iterations.  w is updated in place when allowed.
@@ -1235,10 +1244,14 @@ omt_status omt_autotune(omt_handle h, int32_t iters_per_trial, int32_t *best_t, 
     double bUs = 1e300, b1Us = 1e300;
     int b1R = 0;
     const int Ts[] = {1, 2, 4, 8};
-    const int Rs[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
     for (int T : Ts) {
         if (e != hipSuccess || st != OMT_OK) break;
         if (!step_supported(r.dtype, r.k, r.gk, r.lb, T, r.comp)) continue;
+        // a fixed ladder plus the one-round rule's rows and their neighbours
+        std::vector<int> Rs = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
+        const int rr = rule_rows(h, T);
+        for (int d = -2; d <= 2; ++d)
+            if (rr + d >= 1 && std::find(Rs.begin(), Rs.end(), rr + d) == Rs.end()) Rs.push_back(rr + d);
         for (int rows : Rs) {
             if (rows > r.m && rows != 2) continue;
             if ((e = restore()) != hipSuccess) break;
