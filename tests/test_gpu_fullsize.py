@@ -24,12 +24,15 @@ def _samples(m, n, rng, count):
     return fixed + rand
 
 
-def _check_cone(torch, d, iters, tblock=0, rows=0, nsamp=8, tol_rel=2e-5):
+def _check_cone(torch, d, iters, tblock=0, rows=0, nsamp=8, tol_rel=2e-5, tune=False):
     from paper_1712_10279_amd import omt
     r0, r1 = cast_inputs(d["rho0"], d["rho1"], "f32")
     m, n, k = r0.shape
     s = omt.Solver(to_dev(torch, d["rho0"], torch.float32), to_dev(torch, d["rho1"], torch.float32), d["edges"],
                    alpha=d["alpha"], tau=d["tau"], tblock=tblock, rows_per_wave=rows)
+    if tune:
+        T, R, us = s.autotune()
+        note(f"autotuned shape: T {T}, {R} rows per wave, {us:.2f} us per iteration")
     s.solve(iters, 0.0, 64)
     g = gpu_state_np(s)
     p = O.Problem(m, n, k, edges=d["edges"], alpha=d["alpha"], tau=d["tau"])
@@ -51,11 +54,23 @@ def _check_cone(torch, d, iters, tblock=0, rows=0, nsamp=8, tol_rel=2e-5):
 
 
 def test_large_grid_sampled_cones():
-    """1024x1024, k=8 path, FP32, the benchmark's default launch shape."""
+    """1024x1024, k=8 path, FP32, in the launch shape the benchmark takes
+    from the autotuner."""
     torch = cuda()
     d = I.path8_1024()
-    note("case: 1024x1024 k8 path, 24 iterations, sampled cones")
-    _check_cone(torch, d, 24)
+    note("case: 1024x1024 k8 path, 24 iterations, autotuned shape, sampled cones")
+    _check_cone(torch, d, 24, tune=True)
+
+
+@pytest.mark.parametrize("tblock,rows", [(1, 0), (2, 10)])
+def test_large_grid_sampled_cones_fixed_shapes(tblock, rows):
+    """1024x1024, k=8 path, FP32: single-iteration launches with the default
+    rows, and two iterations per launch with 10 rows per wave (the shape the
+    autotuner picks on MI355X)."""
+    torch = cuda()
+    d = I.path8_1024()
+    note(f"case: 1024x1024 k8 path, 24 iterations, T={tblock} rows={rows}, sampled cones")
+    _check_cone(torch, d, 24, tblock=tblock, rows=rows)
 
 
 def test_rgb_grid_sampled_cones_blocked():
