@@ -316,7 +316,7 @@ def main():
         print(json.dumps(fn(a)), flush=True)
         return
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {a.gpus})",
+        print(f"bench.py runs on one GPU only: the library has no multi-GPU path (asked for --gpus {a.gpus})",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

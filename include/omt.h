@@ -55,7 +55,7 @@ typedef enum {
     OMT_EDEVICE = 6,       /* a HIP call failed */
     OMT_ENOTCONV = 7,      /* tol not reached within max_iters; outputs are valid */
     OMT_EDIVERGED = 8,     /* a check found a non-finite residual */
-    OMT_EUNSUPPORTED = 9   /* valid request this build does not provide (e.g. k > 8) */
+    OMT_EUNSUPPORTED = 9   /* valid request the library is not compiled for (e.g. k > 8) */
 } omt_status;
 
 /* Norms of Sec. 6.2. */
@@ -77,7 +77,7 @@ typedef enum { OMT_F32 = 0, OMT_F64 = 1 } omt_dtype;
  * FP32 spacing of phi are not lost. Ignored for OMT_F64. */
 #define OMT_FLAG_COMPENSATED_PHI 1u
 
-/* Largest channel count of this build. */
+/* Largest channel count compiled into the library. */
 #define OMT_MAX_CHANNELS 8
 
 typedef struct {

@@ -1810,7 +1810,7 @@ const char *omt_strerror(omt_status s)
         case OMT_EDEVICE: return "HIP error";
         case OMT_ENOTCONV: return "tolerance not reached";
         case OMT_EDIVERGED: return "iteration diverged";
-        case OMT_EUNSUPPORTED: return "unsupported by this build";
+        case OMT_EUNSUPPORTED: return "not compiled into this library";
         default: return "unknown status";
     }
 }
