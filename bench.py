@@ -270,7 +270,8 @@ def bench_matrix(a):
     dt, comp, label = _precision(a, "f32comp")
     D = I.dti_like(256)
     dev = lambda x: torch.as_tensor(x, dtype=dt, device="cuda")
-    s = omt.MatrixSolver(dev(D["lam0"]), dev(D["lam1"]), D["L"], alpha=1.0, tau=60.0, compensated=comp)
+    s = omt.MatrixSolver(dev(D["lam0"]), dev(D["lam1"]), D["L"], alpha=1.0, tau=60.0, compensated=comp,
+                         tblock=a.tblock)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it, info = 0, None
@@ -285,22 +286,25 @@ def bench_matrix(a):
     M01, _ = s.distance()
     print(f"# matrix 256: {it} it, {el:.2f} s, M {M01:.6g}, gap {info['rel_gap']:.2e}", file=sys.stderr, flush=True)
     # throughput of the step kernel on a 1024 x 1024 field
+    # (two iterations per launch in FP32, the library's default at this size)
+    T = a.tblock if a.tblock > 0 else (2 if dt == torch.float32 else 1)
     B = I.dti_like(1024)
-    s2 = omt.MatrixSolver(dev(B["lam0"]), dev(B["lam1"]), B["L"], alpha=1.0, tau=60.0, compensated=comp)
+    s2 = omt.MatrixSolver(dev(B["lam0"]), dev(B["lam1"]), B["L"], alpha=1.0, tau=60.0, compensated=comp, tblock=T)
     s2.solve(64, 0.0, 64)
-    us = s2.time_steps(0, a.timing_launches)
+    us = s2.time_steps(0, max(1, a.timing_launches // T) * T)
     K, KW = 6, 6
     per_px = (7 * K + 2 * KW) * (8 if dt == torch.float64 else 4) + (2 * K * 4 if comp else 0)
-    bytes_launch = per_px * 1024 * 1024
+    bytes_launch = per_px * 1024 * 1024 * T
     ach = bytes_launch / us / 1e3
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": None, "kernel": "pdhg_step_kernel (matrix kind, K=6 coordinates, 6 transfer coordinates)",
+            "traffic": None,
+            "kernel": f"pdhg_step_kernel (matrix kind, K=6 coordinates, 6 transfer coordinates, T = {T})",
             "bytes_per_launch": bytes_launch, "us_per_launch": us}
     return _line("matrix OMT time to 1e-3 relative duality gap", el, "s", it, 0, el * 1e3 / it, dtype=_dtype_name(dt),
                  config={"workload": "momt_256x256_real3x3_dti_L", "gap": gap, "tau": 60.0, "alpha": 1.0,
                          "precision": label, "parallelism": "single-gpu"},
                  roofline=roof, M=M01, rel_gap=info["rel_gap"], iterations=it,
-                 cell_iter_per_s=1024 * 1024 / (us * 1e-6))
+                 cell_iter_per_s=1024 * 1024 * T / (us * 1e-6))
 
 
 def main():

@@ -57,6 +57,11 @@ typedef struct {
     omt_dtype dtype;    /* of the data, state and iterates                         */
     int32_t flags;      /* OMT_FLAG_COMPENSATED_PHI (FP32 only)                    */
     int32_t rows_per_wave; /* 0: library default                                   */
+    int32_t tblock;     /* iterations per pass over HBM: 1 or 2 (2: FP32 with the
+                           Frobenius or entry-wise norms, k x k coordinates <= 6, else
+                           OMT_EUNSUPPORTED); 0: 2 where allowed on grids whose
+                           single-iteration strips take 4 or more rows, else 1.  Every
+                           value gives the same iterates bit for bit.             */
 } omt_matrix_params;
 
 /* Defaults: alpha 1, tau 1, Frobenius U, entry-wise W (the setting of the
@@ -95,8 +100,9 @@ omt_status omt_matrix_grad(omt_matrix_handle h, void *dM_dLambda0, void *dM_dLam
  * m*n*k*k entries each, W m*n*l*k*k entries ([i][j][s][a][b]). */
 omt_status omt_matrix_get_state(omt_matrix_handle h, void *Phi, void *Ux, void *Uy, void *W);
 
-/* As omt_time_steps for the coordinate problem (one iteration per launch):
- * mean microseconds per step launch over n timed launches. */
+/* As omt_time_steps for the coordinate problem, in the solve's launch shape
+ * (T = tblock or its default iterations per launch; n must be a multiple of
+ * T): mean microseconds per step launch over n / T timed launches. */
 omt_status omt_matrix_time_steps(omt_matrix_handle h, int32_t rows_per_wave, int64_t n, double *us_per_launch);
 
 omt_status omt_matrix_destroy(omt_matrix_handle h);

@@ -1896,6 +1896,7 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
 
     if (p->dtype != OMT_F32 && p->dtype != OMT_F64) return fail(OMT_EINVAL, "unknown dtype %d", p->dtype);
     if (p->rows_per_wave < 0) return fail(OMT_EINVAL, "rows_per_wave must be >= 0");
+    if (p->tblock < 0 || p->tblock > 2) return fail(OMT_EINVAL, "tblock must be 0, 1 or 2 (got %d)", p->tblock);
     const int k = p->k, l = p->n_L;
     const bool real = p->real != 0;
     ms.k = k;
@@ -1987,7 +1988,7 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
     r.wnorm = p->wnorm == OMT_M_FRO ? 1 : p->wnorm == OMT_M_L1 ? 2 : 3;
     r.dtype = p->dtype;
     r.comp = (p->flags & OMT_FLAG_COMPENSATED_PHI) && p->dtype == OMT_F32;
-    r.tblock = 1;
+    r.tblock = p->tblock;
     r.rows = p->rows_per_wave;
     r.h = p->h > 0.0 ? p->h : 1.0 / double(std::max(r.m, r.n) - 1);
     r.lmax = lmax;
@@ -2021,6 +2022,9 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
     if (!fields_fit(r))
         return fail(OMT_EUNSUPPORTED, "a field of %d x %d x %d %s coordinates exceeds 2 GiB", r.m, r.n,
                     std::max(2 * r.k, r.lb), r.dtype == OMT_F64 ? "FP64" : "FP32");
+    if (r.tblock > 1 && !step_supported(r.dtype, r.k, r.gk, r.lb, r.tblock, r.comp))
+        return fail(OMT_EUNSUPPORTED, "no %d-iteration step for %s %d coordinates with these norms", r.tblock,
+                    r.dtype == OMT_F64 ? "FP64" : "FP32", r.k);
     return OMT_OK;
 }
 
@@ -2187,7 +2191,7 @@ omt_status omt_matrix_get_state(omt_matrix_handle h, void *Phi, void *Ux, void *
 omt_status omt_matrix_time_steps(omt_matrix_handle h, int32_t rows_per_wave, int64_t n, double *us_per_launch)
 {
     if (!h) return fail(OMT_EINVAL, "handle is NULL");
-    return omt_time_steps(h->c, 1, rows_per_wave, n, us_per_launch);
+    return omt_time_steps(h->c, tblock_of(h->c), rows_per_wave, n, us_per_launch);
 }
 
 omt_status omt_matrix_destroy(omt_matrix_handle h)

@@ -82,11 +82,18 @@ hipError_t occ_one(int *blocks)
                                                          WAVE * STEP_WAVES_PER_WG, 0);
 }
 
+// the matrix kind with Frobenius or entry-wise norms also runs two
+// iterations per pass in FP32 (not the 9-coordinate complex 3 x 3 kind)
+constexpr bool MAT_T2 = OMT_K <= 6;
+
 template <int GK, int L>
 hipError_t occ_T(const StepLaunch &Lc, int *blocks)
 {
     if (Lc.dtype == 1) return occ_one<double, GK, L, 1, false>(blocks);
     if (Lc.T == 1) return Lc.comp ? occ_one<float, GK, L, 1, true>(blocks) : occ_one<float, GK, L, 1, false>(blocks);
+    if constexpr (GK == G_MATRIX && MAT_T2) {
+        if (Lc.T == 2) return Lc.comp ? occ_one<float, GK, L, 2, true>(blocks) : occ_one<float, GK, L, 2, false>(blocks);
+    }
     if constexpr (GK != G_DENSE && !is_matrix_kind(GK)) {
         switch (Lc.T) {
             case 2: return Lc.comp ? occ_one<float, GK, L, 2, true>(blocks) : occ_one<float, GK, L, 2, false>(blocks);
@@ -132,6 +139,9 @@ hipError_t dispatch_T(const StepLaunch &Lc)
         return hipErrorInvalidValue;
     }
     if (Lc.T == 1) return Lc.comp ? launch_one<float, GK, L, 1, true>(Lc) : launch_one<float, GK, L, 1, false>(Lc);
+    if constexpr (GK == G_MATRIX && MAT_T2) {
+        if (Lc.T == 2) return Lc.comp ? launch_one<float, GK, L, 2, true>(Lc) : launch_one<float, GK, L, 2, false>(Lc);
+    }
     if constexpr (GK != G_DENSE && !is_matrix_kind(GK)) {
         switch (Lc.T) {
             case 2: return Lc.comp ? launch_one<float, GK, L, 2, true>(Lc) : launch_one<float, GK, L, 2, false>(Lc);
@@ -246,6 +256,7 @@ bool OMT_CAT(step_supported_k, OMT_K)(int dtype, int gk, int lb, int T, bool com
     ok = ok || (L_MAT > 0 && OMT_K != 9 && gk == G_MATNUC && (lb == L_MAT || (L_MAT2 > 0 && lb == L_MAT2)));
     if (!ok) return false;
     if (dtype == 1) return T == 1 && !comp;
+    if (gk == G_MATRIX) return T == 1 || (MAT_T2 && T == 2);
     if (gk == G_DENSE || is_matrix_kind(gk)) return T == 1;
     return t_ok(T);
 }

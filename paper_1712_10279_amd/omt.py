@@ -43,7 +43,7 @@ class MatrixParams(C.Structure):
                 ("L", C.POINTER(C.c_double)), ("real", C.c_int32),
                 ("alpha", C.c_double), ("tau", C.c_double), ("mu", C.c_double), ("nu", C.c_double),
                 ("h", C.c_double), ("unorm", C.c_int32), ("wnorm", C.c_int32), ("dtype", C.c_int32),
-                ("flags", C.c_int32), ("rows_per_wave", C.c_int32)]
+                ("flags", C.c_int32), ("rows_per_wave", C.c_int32), ("tblock", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -443,7 +443,7 @@ class BatchSolver:
 # ----------------------------------------------------------------- matrix OMT
 
 def make_matrix_params(m, n, L, real, alpha=1.0, tau=1.0, unorm=M_FRO, wnorm=M_L1, mu=0.0, nu=0.0, h=0.0,
-                       compensated=False, rows_per_wave=0, dtype=F32):
+                       compensated=False, rows_per_wave=0, tblock=0, dtype=F32):
     """(MatrixParams, keep-alive array) for the matrix C ABI; L is an
     (l, k, k) real or complex array of Hermitian matrices."""
     Lc = np.asarray(L)
@@ -459,6 +459,7 @@ def make_matrix_params(m, n, L, real, alpha=1.0, tau=1.0, unorm=M_FRO, wnorm=M_L
     p.unorm, p.wnorm, p.dtype = int(unorm), int(wnorm), int(dtype)
     p.flags = FLAG_COMPENSATED_PHI if compensated else 0
     p.rows_per_wave = int(rows_per_wave)
+    p.tblock = int(tblock)
     return p, Lc
 
 

@@ -135,8 +135,19 @@ def test_matrix_step_sizes_and_coordinates():
     (np.stack([PAULI["x"], PAULI["z"], PAULI["y"]]), False, {}, omt.EUNSUPPORTED),  # 12 transfer coordinates
     (L_DTI, True, {"tau": 0.0}, omt.EINVAL),
     (L_DTI, True, {"mu": 1.0}, omt.ESTEP),
+    (L_DTI, True, {"tblock": 3}, omt.EINVAL),              # one or two iterations per pass
+    (L_DTI, True, {"tblock": 2, "unorm": omt.M_NUC}, omt.EUNSUPPORTED),   # nuclear: one per pass
+    (L_DTI, True, {"tblock": 2, "dtype": omt.F64}, omt.EUNSUPPORTED),     # FP64: one per pass
+    (np.stack([np.array([[1, 1j, 0], [-1j, 0, 2], [0, 2, -1]]), np.diag([1.0, 0.0, -2.0]).astype(complex)]), False,
+     {"tblock": 2}, omt.EUNSUPPORTED),                   # complex 3 x 3: one per pass
 ])
 def test_matrix_invalid_parameters(L, real, kw, status):
     with pytest.raises(omt.OMTError) as e:
         omt.matrix_resolve(12, 12, L, real, **kw)
     assert e.value.status == status
+
+
+def test_matrix_two_iterations_per_pass_accepted():
+    for L, real in ((L_DTI, True), (np.stack([PAULI["x"], PAULI["z"]]), False)):
+        for unorm, wnorm in ((omt.M_FRO, omt.M_L1), (omt.M_L1, omt.M_FRO)):
+            omt.matrix_resolve(12, 12, L, real, tblock=2, unorm=unorm, wnorm=wnorm)

@@ -123,6 +123,33 @@ def test_fp32_nuclear_within_tolerance():
     assert abs(M - r["primal"]) <= 1e-4 * r["primal"]
 
 
+@pytest.mark.parametrize("case", ["dti_real_k3", "pauli_real_k2", "complex_k2", "dti_plus_one_real_k3"])
+@pytest.mark.parametrize("comp", [False, True])
+def test_two_iterations_per_pass_are_bit_identical(case, comp):
+    """FP32 launches of two iterations (T = 2: one HBM pass, halo lanes and
+    rows recomputed) give the bits of single-iteration launches, for any
+    strip height, in timed launches and in a solve with checks."""
+    torch = cuda()
+    note(f"case: matrix T=2 bits {case} comp={comp}")
+    kw = dict(f64=False, alpha=0.8, tau=2.0, compensated=comp, unorm=MO.FRO, wnorm=MO.L1)
+    ref = _solver(torch, case, tblock=1, **kw)[0]
+    ref.time_steps(0, 48)
+    a = ref.get_state()
+    for rows in (0, 5):
+        s = _solver(torch, case, tblock=2, rows_per_wave=rows, **kw)[0]
+        s.time_steps(rows, 48)
+        b = s.get_state()
+        for key in ("phi", "ux", "uy", "w"):
+            assert torch.equal(a[key], b[key]), (case, comp, rows, key)
+    s1 = _solver(torch, case, tblock=1, **kw)[0]
+    s2 = _solver(torch, case, tblock=2, **kw)[0]
+    i1, i2 = s1.solve(200, 0.0, 32), s2.solve(200, 0.0, 32)
+    assert i1["residual"] == i2["residual"] and i1["primal"] == i2["primal"]
+    a, b = s1.get_state(), s2.get_state()
+    for key in ("phi", "ux", "uy", "w"):
+        assert torch.equal(a[key], b[key]), (case, comp, "solve", key)
+
+
 @pytest.mark.parametrize("case", ["dti_real_k3", "complex_k2", "complex_k3"])
 def test_fp64_gradient_is_the_oracle_potential(case):
     torch = cuda()
