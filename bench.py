@@ -385,7 +385,7 @@ def main():
                   "mass_residual": info["mass_residual"]},
     }
     if not a.no_cpu:
-        iters = a.cpu_iters or max(2, int(40 * (1024 * 1024 * 8) / (cells * k)))
+        iters = a.cpu_iters or max(2, int(60 * (1024 * 1024 * 8) / (cells * k)))
         line["cpu_baseline"] = cpu_baseline(d, iters)
     print(json.dumps(line), flush=True)
 
