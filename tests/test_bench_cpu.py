@@ -24,8 +24,10 @@ def test_traffic_only_for_the_profiled_source_and_shape():
     assert entries, "no counter summary committed"
     for key, e in entries.items():
         T, size = int(key.split("_")[0][1:]), int(key.split("_n")[1])
-        # the committed counters were taken on the committed kernel source
-        assert e["kernel_sha"] == bench._kernel_hash(), key
+        # reported for the source the counters were taken on, else null
+        if e["kernel_sha"] != bench._kernel_hash():
+            assert bench._traffic(T, size, e.get("rows", 0)) is None
+            continue
         assert bench._traffic(T, size, e.get("rows", 0)) == e["bytes_per_launch"]
         # other shapes and sizes have no counters
         assert bench._traffic(T, size, (e.get("rows") or 1) + 1) is None
