@@ -21,6 +21,20 @@ MUTANTS = [
     ("transposed gradient", "gy[I3(i, j, c, n, k)] = (j < n - 1) ? (phi[I3(i, j + 1, c, n, k)]", "gy[I3(i, j, c, n, k)] = (j < n - 1) ? (phi[I3(i + 1 < m ? i + 1 : i, j, c, n, k)]"),
     ("w threshold without alpha", "orc_shrink_w(p->wnorm, l, b, p->alpha * p->nu);", "orc_shrink_w(p->wnorm, l, b, p->nu);"),
     ("mu rule of S-OMT used for V-OMT", "p->mu = p->h * p->h / (32.0 * p->tau);", "p->mu = p->h * p->h / (16.0 * p->tau);"),
+    ("regularised w factor with mu", "for (int e = 0; e < l; ++e) b[e] /= 1.0 + 2.0 * p->nu * p->eps;",
+     "for (int e = 0; e < l; ++e) b[e] /= 1.0 + 2.0 * p->mu * p->eps;"),
+    ("regularised w factor dropped", "for (int e = 0; e < l; ++e) b[e] /= 1.0 + 2.0 * p->nu * p->eps;",
+     "for (int e = 0; e < l; ++e) b[e] /= 1.0;"),
+    ("w dropped from the regulariser's objective", "for (size_t q = 0; q < Pl; ++q) sq += w1[q] * w1[q];",
+     "for (size_t q = 0; q < Pl; ++q) sq += 0.0 * w1[q];"),
+    ("sign of div_G in the constraint residual", "double r = t1[q] + (l > 0 ? t2[q] : 0.0) + f[q];",
+     "double r = t1[q] - (l > 0 ? t2[q] : 0.0) + f[q];"),
+    ("div_x dropped from the constraint residual", "double r = t1[q] + (l > 0 ? t2[q] : 0.0) + f[q];",
+     "double r = (l > 0 ? t2[q] : 0.0) + f[q];"),
+    ("constraint residual not relative to ||f||", "info->mass_residual = ff > 0 ? sqrt(met[3] / ff) : 0.0;",
+     "info->mass_residual = ff > 0 ? sqrt(met[3]) : 0.0;"),
+    ("gap relative to the dual", "info->rel_gap = met[1] > 0 ? (met[1] - met[2]) / met[1] : 0.0;",
+     "info->rel_gap = met[1] > 0 ? (met[1] - met[2]) / met[2] : 0.0;"),
 ]
 
 

@@ -12,6 +12,8 @@ import os
 import numpy as np
 import pytest
 
+from paper_1712_10279_amd import inputs as I
+
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
@@ -228,3 +230,40 @@ def test_second_iterate_worked_by_hand(orc):
     assert np.allclose(s2["w"][:, :, 0].ravel(), ev(g["w2"]), atol=1e-16)
     assert np.allclose(s2["phi"][:, :, 0].ravel(), ev(g["phi2_ch0"]), atol=1e-15)
     assert np.allclose(s2["phi"][:, :, 1].ravel(), ev(g["phi2_ch1"]), atol=1e-15)
+
+
+def test_second_iterate_check_quantities_worked_by_hand(orc):
+    """R^k (Sec. 6.1, 1/nu on the w block), primal and dual objectives, gap and
+    constraint residual of the step 1 -> 2 of the hand-worked 2x2x2 problem."""
+    with open(os.path.join(GOLD, "second_iterate_2x2x2.json")) as fh:
+        g = json.load(fh)
+    s = (1 - 1 / math.sqrt(2)) / 32
+    ev = lambda x: eval(x, {"s": s, "sqrt": math.sqrt})  # noqa: E731
+    p = orc.Problem(2, 2, 2, edges=[(0, 1)], alpha=0.5, tau=1.0)
+    f = np.zeros((2, 2, 2))
+    f[:, :, 0] = np.array(g["f_ch0"], float).reshape(2, 2)
+    s1 = orc.step(p, f, orc.zero_state(p))
+    s2 = orc.step(p, f, s1)
+    met = orc.metrics(p, f, s1, s2)
+    assert met[0] == pytest.approx(ev(g["R2"]), rel=1e-13)
+    assert met[1] == pytest.approx(ev(g["primal2"]), rel=1e-13)
+    assert met[2] == pytest.approx(ev(g["dual2"]), rel=1e-13)
+    assert met[3] == pytest.approx(ev(g["mass2_sq"]), rel=1e-13)
+    assert met[4] == pytest.approx(ev(g["fnorm2"]), rel=1e-15)
+    # the same through the solver's report after exactly two iterations
+    r = orc.solve(p, f, 2, 0.0, 64)
+    P, D = ev(g["primal2"]), ev(g["dual2"])
+    assert r["iters"] == 2
+    assert r["mass_residual"] == pytest.approx(math.sqrt(ev(g["mass2_sq"]) / ev(g["fnorm2"])), rel=1e-13)
+    assert r["rel_gap"] == pytest.approx((P - D) / P, rel=1e-13)
+    assert r["residual"] == pytest.approx(math.sqrt(ev(g["R2"]) / (p.tau * ev(g["fnorm2"]))), rel=1e-13)
+
+
+@pytest.mark.parametrize("k,edges", [(3, I.TRIANGLE), (4, I.path_edges(4)), (1, np.zeros((0, 2)))])
+def test_mass_residual_is_one_after_the_first_step(orc, k, edges):
+    """From the zero start the first step leaves u = w = 0 (Sec. 7.2), so the
+    constraint residual div_x u + div_G w + f equals f: relative value 1."""
+    r0, r1 = I.random_pair(41, 7, 9, k)
+    r = orc.solve_pair(r0, r1, edges, max_iters=1)
+    assert r["mass_residual"] == 1.0
+    assert r["primal"] == 0.0

@@ -240,3 +240,59 @@ def test_regularisation_vanishes_as_eps_goes_to_zero(orc):
     assert all(g >= -1e-10 for g in gaps)
     assert gaps[0] > gaps[1] > gaps[2]
     assert gaps[2] < 1e-3 * base
+
+
+@pytest.mark.parametrize("k,edges,cost", [
+    (2, [(0, 1)], [1.0]),
+    (2, [(0, 1)], [2.0]),
+    (3, I.path_edges(3), [1.0, 1.0]),
+    (4, I.path_edges(4), [1.0, 0.5, 1.5]),
+])
+def test_regularised_pixel_balanced_closed_form(orc, k, edges, cost):
+    # Quadratic regularisation (Sec. 9) with the transfer w active.  Every
+    # pixel carries the same total mass in rho0 and rho1, and the graph is a
+    # path.  With alpha and eps small against h no spatial flux pays: u = 0,
+    # and the constraint div_G w = rho0 - rho1 (div_G = -D diag(1/c), Sec. 3.1)
+    # fixes the transfer on the path's edge e = (e, e+1) at every pixel:
+    #   w_e = c_e * sum_{c <= e} (rho1 - rho0)_c.
+    # The unique optimum (the objective is strictly convex) therefore has
+    #   V_eps = sum_pixels sum_e (alpha |w_e| + eps w_e^2).
+    # Its dual potential satisfies the transfer's optimality condition at every
+    # pixel, (phi_a - phi_b) / c_e = alpha sign(w_e) + 2 eps w_e, and the
+    # potential built from these differences has spatial differences below
+    # h / sqrt(2) per channel by the choice of alpha and eps (so u = 0 is
+    # optimal: the dual constraint of the isotropic norm holds).
+    m, n = 5, 6
+    rng = np.random.default_rng(31 + k)
+    tot = rng.random((m, n)) + 0.5
+    r0 = tot[:, :, None] * rng.dirichlet(np.ones(k), size=(m, n))
+    r1 = tot[:, :, None] * rng.dirichlet(np.ones(k), size=(m, n))
+    scale = r0.sum()
+    r0 /= scale
+    r1 /= scale
+    cost = np.asarray(cost, float)
+    h = 1.0 / (max(m, n) - 1)
+    F = np.cumsum(r1 - r0, axis=2)[:, :, :-1]          # sum_{c <= e} (rho1 - rho0)_c
+    w_star = cost[None, None, :] * F
+    wmax = np.abs(w_star).max()
+    # per-pixel potential range <= sum_e c_e (alpha + 2 eps |w_e|); spatial
+    # differences at most twice that; need sqrt(2) * 2 * range <= h
+    budget = h / (2 * np.sqrt(2)) / cost.sum()
+    alpha = 0.45 * budget
+    eps = 0.45 * budget / (2 * wmax)
+    V = (alpha * np.abs(w_star) + eps * w_star ** 2).sum()
+    r = orc.solve_pair(r0, r1, edges, alpha=alpha, eps=eps, cost=cost, max_iters=2000000, tol=1e-12)
+    assert r["converged"]
+    st = r["state"]
+    assert np.abs(st["ux"]).max() < 1e-9 * wmax and np.abs(st["uy"]).max() < 1e-9 * wmax
+    assert np.allclose(st["w"], w_star, rtol=0, atol=1e-8 * wmax)
+    assert r["primal"] == pytest.approx(V, rel=1e-9)
+    # the regulariser term is a sizeable part of V, so dropping it is visible
+    assert (eps * w_star ** 2).sum() > 0.05 * V
+    # transfer optimality: (phi_a - phi_b) / c_e = alpha sign(w_e) + 2 eps w_e
+    phi = st["phi"]
+    dG = (phi[:, :, :-1] - phi[:, :, 1:]) / cost[None, None, :]
+    want = alpha * np.sign(w_star) + 2 * eps * w_star
+    assert np.abs(dG - want).max() < 1e-6 * alpha
+    # at the optimum the constraint holds: relative residual -> 0
+    assert r["mass_residual"] < 1e-8
