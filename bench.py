@@ -1,12 +1,13 @@
-"""Throughput of the fused PDHG step on one MI355X.
+"""Throughput of the fused PDHG path on one MI355X.
 
 Workload: vector OMT on a 1024 x 1024 grid, k = 8 channels on a path graph
-(7 edges), alpha 1, FP32 iterates with FP64 reductions, seeded 16-bump
-Gaussian mixtures with mass moved between channels (see
-``paper_1712_10279_amd/inputs.py``).  One step is one PDHG iteration of the
-whole path (gradient, both shrinks, extrapolation, divergences, dual ascent)
-over the grid; the solve takes its residual/objective check every 64
-iterations inside the timed region, as a real solve does.
+(7 edges), alpha 1, tau 3, FP32 iterates with FP64 reductions, seeded
+16-bump Gaussian mixtures with mass moved between channels (see
+``paper_1712_10279_amd/inputs.py``), 20,000 iterations.  One step is one
+whole solve: the set-up (mass check, source term, zero state), the 20,000
+iterations (gradient, both shrinks, extrapolation, divergences, dual ascent)
+with the residual/objective check every 64 iterations, then the distance and
+the gradient potential.
 
 Prints one JSON line.  ``value`` is cell-iterations/s (cells = grid pixels,
 each carrying all k channels and l edges) with the inputs resident in HBM.
@@ -30,8 +31,11 @@ HBM_PEAK_GBS = 8000.0
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=640)
+    ap.add_argument("--steps", type=int, default=3, help="timed steps; a step is one whole solve of the workload")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=0, help="iterations per solve (0: the workload's 20,000)")
+    ap.add_argument("--tau", type=float, default=0.0, help="dual step (0: the workload's)")
+    ap.add_argument("--no-fp64-check", action="store_true", help="skip the FP64 run that states the FP32 error")
     ap.add_argument("--size", type=int, default=1024, help="grid side (default: the 1024 x 1024 workload)")
     ap.add_argument("--tblock", type=int, default=0, help="iterations per HBM pass (0: library default)")
     ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0: library default)")
@@ -329,36 +333,77 @@ def main():
     from paper_1712_10279_amd import omt
 
     d = I.path8_1024(m=a.size, n=a.size)
+    if a.tau > 0:
+        d["tau"] = a.tau
+    iters = a.iters or d["iters"]
     m, n, k = d["rho0"].shape
     l = len(d["edges"])
     dev = torch.device("cuda:0")
     r0 = torch.as_tensor(d["rho0"], dtype=torch.float32, device=dev)
     r1 = torch.as_tensor(d["rho1"], dtype=torch.float32, device=dev)
-    s = omt.Solver(r0, r1, d["edges"], alpha=d["alpha"], tau=d["tau"], tblock=a.tblock, rows_per_wave=a.rows)
     T, rows = a.tblock, a.rows
     if T == 0 and rows == 0:
         # launch shape (iterations per HBM pass, rows per wave) from the
-        # library's autotuner, before the untimed warm-up; every shape gives
-        # the same iterates bit for bit
+        # library's autotuner, untimed; every shape gives the same iterates
+        # bit for bit
+        s = omt.Solver(r0, r1, d["edges"], alpha=d["alpha"], tau=d["tau"])
         T, rows, _ = s.autotune()
+        del s
     T = T if T > 0 else 1
 
-    if a.warmup:
-        s.solve(a.warmup, 0.0, 64)
+    def one_solve():
+        """One step: the whole path once -- set-up (mass check, source term,
+        zero state), the iterations with their checks, then the distance
+        and the gradient potential."""
+        s = omt.Solver(r0, r1, d["edges"], alpha=d["alpha"], tau=d["tau"], tblock=T, rows_per_wave=rows)
+        info = s.solve(iters, 0.0, 64)
+        V, _ = s.distance()
+        g0, _ = s.grad()
+        return s, info, V, g0
+
+    for _ in range(a.warmup):
+        one_solve()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    info = s.solve(a.steps, 0.0, 64)
+    for _ in range(a.steps):
+        s, info, V, g0 = one_solve()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     cells = m * n
-    value = cells * a.steps / dt
+    value = cells * iters * a.steps / dt
 
-    # dominant kernel: the fused step, timed with HIP events on its own stream
+    # activity of the final iterate: where the shrinks returned non-zero
+    st = s.get_state()
+    u_act = float(((st["u"] != 0).reshape(m, n, -1).any(dim=2)).double().mean())
+    w_act = float(((st["w"] != 0).reshape(m, n, -1).any(dim=2)).double().mean()) if l else 0.0
+
+    # dominant kernel: the fused step, timed with HIP events on its own
+    # stream, from the solved (active) state
     launches = max(1, a.timing_launches // T) * T
     us = s.time_steps(T, rows, launches)
     alg_bytes = (7 * k + 2 * l) * 4 * cells * T
     achieved = alg_bytes / (us * 1e-6) / 1e9
-    V, _ = s.distance()
+    traffic = _traffic(T, a.size, rows)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": f"pdhg_step_kernel (T = {T} iterations per launch)", "us_per_launch": us,
+            "bytes_per_launch": alg_bytes}
+    if traffic:
+        # what the memory system moved (counted bytes) at the same launch time
+        roof["counted_gbs"] = traffic / (us * 1e-6) / 1e9
+        roof["counted_frac"] = roof["counted_gbs"] / HBM_PEAK_GBS
+
+    # error of this FP32 run against an FP64 run of the same problem (the
+    # FP64 path follows the oracle element by element in the tests)
+    fp64 = None
+    if not a.no_fp64_check:
+        s64 = omt.Solver(r0.double(), r1.double(), d["edges"], alpha=d["alpha"], tau=d["tau"])
+        s64.solve(iters, 0.0, 64)
+        V64, _ = s64.distance()
+        g64, _ = s64.grad()
+        fp64 = {"rel_V": abs(V - V64) / V64 if V64 else abs(V), "max_abs_Phi": float((g0.double() - g64).abs().max()),
+                "max_abs_Phi_fp64": float(g64.abs().max()), "V_fp64": V64}
+        del s64
 
     line = {
         "metric": "PDHG cell-iterations/s",
@@ -374,19 +419,18 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": d["name"], "grid": [m, n], "channels": k, "edges": l, "graph": "path",
-                   "alpha": d["alpha"], "tau": d["tau"], "iterations": a.steps, "check_every": 64,
+                   "alpha": d["alpha"], "tau": d["tau"], "iterations_per_step": iters, "check_every": 64,
+                   "step": "one whole solve: set-up, iterations with checks, distance and gradient",
                    "tblock": T, "rows_per_wave": rows, "parallelism": "single-gpu"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(T, a.size, rows),
-                     "kernel": f"pdhg_step_kernel (T = {T} iterations per launch)", "us_per_launch": us,
-                     "bytes_per_launch": alg_bytes},
+        "roofline": roof,
         "pixel_channel_iter_per_s": value * k,
         "solve": {"primal": V, "residual": info["residual"], "rel_gap": info["rel_gap"],
-                  "mass_residual": info["mass_residual"]},
+                  "mass_residual": info["mass_residual"], "u_active": u_act, "w_active": w_act},
+        "fp32_vs_fp64": fp64,
     }
     if not a.no_cpu:
-        iters = a.cpu_iters or max(2, int(60 * (1024 * 1024 * 8) / (cells * k)))
-        line["cpu_baseline"] = cpu_baseline(d, iters)
+        cpu_iters = a.cpu_iters or max(2, int(60 * (1024 * 1024 * 8) / (cells * k)))
+        line["cpu_baseline"] = cpu_baseline(d, cpu_iters)
     print(json.dumps(line), flush=True)
 
 

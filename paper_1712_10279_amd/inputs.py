@@ -225,3 +225,35 @@ def dti_like(side=128, seed=0, bumps=6):
         return matrix_field(r, side, side, 3, bumps, side / 32, side / 12, True, 1e-3, centres=cen, shapes=sh)
 
     return {"lam0": field(cen0, sh0), "lam1": field(cen0, sh1), "lam2": field(cen2, sh0), "L": L_DTI}
+
+
+# ------------------------------------------------------------- warm starts
+
+def warm_state(seed: int, m: int, n: int, k: int, l: int, u_scale: float, w_scale: float,
+               offset: float, slope: float = 2.5, period: float = 32.0):
+    """A seeded synthetic iterate (phi, u, w) in the caller's layout (phi
+    m x n x k, u m x n x k x 2, w m x n x l), for starting both sides from a
+    state in which the shrinks are active.
+
+    Channel c of phi is ``a_c sin(2 pi (i cos t_c + j sin t_c) / period +
+    p_c) + (-1)^c offset / 2`` with the amplitude a_c chosen so that the
+    per-pixel slope (in units of the grid spacing h = 1/(max(m,n)-1)) is
+    ``slope`` times a factor uniform in [0.5, 1.5]: slopes above 1 make
+    the flux shrink return non-zero values, and neighbouring channels apart
+    by more than alpha make the transfer shrink do so.  u and w are uniform
+    in [-u_scale, u_scale] and [-w_scale, w_scale]."""
+    rng = np.random.default_rng(np.random.SeedSequence([200, seed, m, n, k]))
+    h = 1.0 / (max(m, n) - 1)
+    ii = np.arange(m, dtype=np.float64)[:, None]
+    jj = np.arange(n, dtype=np.float64)[None, :]
+    phi = np.zeros((m, n, k))
+    for c in range(k):
+        t = rng.uniform(0.0, 2.0 * np.pi)
+        p = rng.uniform(0.0, 2.0 * np.pi)
+        s = slope * rng.uniform(0.5, 1.5)
+        amp = s * h * period / (2.0 * np.pi)
+        phi[:, :, c] = amp * np.sin(2.0 * np.pi * (ii * np.cos(t) + jj * np.sin(t)) / period + p) \
+            + (0.5 if c % 2 == 0 else -0.5) * offset
+    u = rng.uniform(-u_scale, u_scale, size=(m, n, k, 2))
+    w = rng.uniform(-w_scale, w_scale, size=(m, n, l))
+    return phi, u, w

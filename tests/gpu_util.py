@@ -46,20 +46,38 @@ def note(msg):
 
 
 def cone_oracle(f_full, p_full, pix, iters, state=None):
-    """Oracle values at pixel ``pix`` after ``iters`` iterations from zeros,
-    computed on the crop of radius iters+2 around it: information moves at
-    most one pixel per iteration, so the crop's artificial border cannot
-    reach the centre (where the crop meets the real border, the real border
-    is inside the crop)."""
+    """Oracle values at pixel ``pix`` after ``iters`` iterations from zeros
+    (or from ``state``: full-grid arrays phi (m, n, k), ux, uy (m, n, k) and
+    w (m, n, l)), computed on the crop of radius iters+2 around it:
+    information moves at most one pixel per iteration, so the crop's
+    artificial border cannot reach the centre (where the crop meets the real
+    border, the real border is inside the crop)."""
     m, n, k = f_full.shape
     i, j = pix
     rad = iters + 2
     i0, i1 = max(0, i - rad), min(m, i + rad + 1)
     j0, j1 = max(0, j - rad), min(n, j + rad + 1)
     p = O.Problem(i1 - i0, j1 - j0, k, edges=p_full.edges, cost=p_full.cost, alpha=p_full.alpha, tau=p_full.tau,
-                  mu=p_full.mu, nu=p_full.nu, h=p_full.h, unorm=p_full.unorm, wnorm=p_full.wnorm)
-    r = O.solve(p, f_full[i0:i1, j0:j1], iters, 0.0, 1 << 30)
+                  mu=p_full.mu, nu=p_full.nu, h=p_full.h, unorm=p_full.unorm, wnorm=p_full.wnorm, eps=p_full.eps)
+    st = None
+    if state is not None:
+        st = {key: np.array(state[key][i0:i1, j0:j1], dtype=np.float64) for key in ("phi", "ux", "uy", "w")}
+        # ghost components of the real border (App. A) are zero on both sides
+        if i1 == m:
+            st["ux"][-1] = 0.0
+        if j1 == n:
+            st["uy"][:, -1] = 0.0
+    r = O.solve(p, f_full[i0:i1, j0:j1], iters, 0.0, 1 << 30, state=st)
     s = r["state"]
     ci, cj = i - i0, j - j0
     return {"phi": s["phi"][ci, cj], "ux": s["ux"][ci, cj], "uy": s["uy"][ci, cj],
             "w": s["w"][ci, cj] if p.l else np.zeros(0)}
+
+
+def active_fraction(ux, uy, w):
+    """Fractions of pixels whose flux (any channel, either direction) and
+    whose transfer (any edge) are non-zero; arrays (..., k) and (..., l)."""
+    ux, uy, w = np.asarray(ux), np.asarray(uy), np.asarray(w)
+    ua = float(((ux != 0) | (uy != 0)).reshape(-1, ux.shape[-1]).any(axis=1).mean())
+    wa = float((w != 0).reshape(-1, w.shape[-1]).any(axis=1).mean()) if w.size else 0.0
+    return ua, wa
