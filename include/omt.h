@@ -220,6 +220,35 @@ omt_status omt_autotune(omt_handle h, int32_t iters_per_trial, int32_t *best_t, 
  * measurement; the state advances by n iterations. */
 omt_status omt_time_steps(omt_handle h, int32_t T, int32_t rows_per_wave, int64_t n, double *us_per_launch);
 
+/* ------------------------------------------------- without allocation */
+
+/* Bytes of the device workspace inside the library used by omt_solve_static. */
+#define OMT_STATIC_WORKSPACE_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc and its relatives): one whole solve of the
+ * vector method -- the set-up of omt_create, the iterations of omt_solve,
+ * then V as omt_distance and the gradients as omt_grad -- whose device
+ * workspace is a fixed array inside the library of
+ * OMT_STATIC_WORKSPACE_BYTES per GPU, held from the first call on a GPU
+ * until the process ends.  The call allocates no device, pinned or heap
+ * memory and captures no graph (so it is slower than a handle for short
+ * check intervals).  Arguments as for omt_create / omt_solve; V (host),
+ * d_rho0, d_rho1 (device, m*n*k of the dtype) and info are each nullable.
+ * Iterates, V and gradients are bit-identical to omt_create + omt_solve +
+ * omt_distance + omt_grad on the same problem.
+ * Limits and sharing: a problem whose omt_workspace_bytes() exceed
+ * OMT_STATIC_WORKSPACE_BYTES (for example FP32 with k = 3 above about
+ * 790 x 790) is rejected with OMT_ENOMEM before any device work.  Every
+ * call on one GPU uses that GPU's single array and starts by zeroing the
+ * state it holds, so calls that overlap on one GPU (other threads or
+ * streams) race and must be serialised by the caller.  The stream is
+ * synchronised before the call returns.  Returns OMT_ENOTCONV as omt_solve
+ * (outputs valid). */
+omt_status omt_solve_static(const omt_params *p, const void *rho0, const void *rho1, int64_t max_iters, double tol,
+                            int32_t check_every, double *V, void *d_rho0, void *d_rho1, omt_info *info,
+                            void *stream);
+
 const char *omt_strerror(omt_status s);
 const char *omt_last_error(void);
 int32_t omt_version(void);

@@ -8,12 +8,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -135,7 +137,9 @@ using namespace omt;
 
 namespace {
 
-thread_local std::string g_last_error;
+// detail of the last failure on this thread (fixed storage: no call allocates
+// to report an error)
+thread_local char g_last_error[512];
 
 omt_status fail(omt_status s, const char *fmt, ...)
 {
@@ -144,7 +148,7 @@ omt_status fail(omt_status s, const char *fmt, ...)
     va_start(ap, fmt);
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
-    g_last_error = buf;
+    std::memcpy(g_last_error, buf, sizeof(buf));
     return s;
 }
 
@@ -156,8 +160,9 @@ omt_status fail(omt_status s, const char *fmt, ...)
 
 // ------------------------------------------------------------------ graph
 
-// Eigenvalues of a symmetric matrix by the cyclic Jacobi method.
-std::vector<double> jacobi_eigenvalues(std::vector<double> A, int k)
+// Eigenvalues of a symmetric k x k matrix by the cyclic Jacobi method, in
+// place: A (row-major, overwritten) and ev[k] are the caller's storage.
+void jacobi_eigenvalues(double *A, int k, double *ev)
 {
     for (int sweep = 0; sweep < 64; ++sweep) {
         double off = 0.0, tot = 0.0;
@@ -186,27 +191,19 @@ std::vector<double> jacobi_eigenvalues(std::vector<double> A, int k)
                 }
             }
     }
-    std::vector<double> ev(k);
     for (int p = 0; p < k; ++p) ev[p] = A[p * k + p];
-    return ev;
-}
-
-double jacobi_lambda_max(std::vector<double> A, int k)
-{
-    double mx = 0.0;
-    for (double v : jacobi_eigenvalues(std::move(A), k)) mx = std::max(mx, v);
-    return mx;
 }
 
 struct Resolved {
     int m, n, k, l, gk, lb;
-    std::vector<int32_t> edges;
-    std::vector<double> cost;
+    // fixed-size members: resolving a vector problem allocates nothing
+    std::array<int32_t, 2 * LMAX> edges;
+    std::array<double, LMAX> cost;
     double alpha, tau, mu, nu, h, lmax, eps;
     int unorm, wnorm, dtype;
     bool comp;
     int tblock, rows;
-    std::vector<int> cls;  // mass class per channel (-1: no mass constraint, no mean removed)
+    std::array<int, KMAX> cls;  // mass class per channel (-1: no mass constraint, no mean removed)
     int ncls;
     // matrix method (G_MATRIX): dense operator, row c / column e at
     // gmat[c * LMAX + e], and the group weights of the grouped norms
@@ -264,8 +261,9 @@ omt_status resolve(const omt_params *p, Resolved &r)
     r.n = p->n;
     r.k = p->k;
     r.l = p->n_edges;
-    r.edges.assign(p->edges, p->edges + 2 * r.l);
-    r.cost.assign(r.l, 1.0);
+    if (r.l > LMAX) return fail(OMT_EUNSUPPORTED, "%d edges exceed %d", r.l, LMAX);
+    for (int q = 0; q < 2 * r.l; ++q) r.edges[q] = p->edges[q];
+    for (int e = 0; e < r.l; ++e) r.cost[e] = 1.0;
     if (p->edge_cost)
         for (int e = 0; e < r.l; ++e) r.cost[e] = p->edge_cost[e];
     for (int e = 0; e < r.l; ++e) {
@@ -277,7 +275,6 @@ omt_status resolve(const omt_params *p, Resolved &r)
         for (int f = 0; f < e; ++f)
             if (r.edges[2 * f] == a && r.edges[2 * f + 1] == b) return fail(OMT_EGRAPH, "duplicate edge (%d, %d)", a, b);
     }
-    if (r.l > LMAX) return fail(OMT_EUNSUPPORTED, "%d edges exceed %d", r.l, LMAX);
     // graph kind: compiled incidence for the path and the complete graph in
     // canonical edge order, the dense matrix otherwise
     {
@@ -314,7 +311,7 @@ omt_status resolve(const omt_params *p, Resolved &r)
     // lambda_max(-Delta_G), -Delta_G = D diag(1/c^2) D^T (Sec. 3.1)
     r.lmax = 0.0;
     if (r.l > 0) {
-        std::vector<double> A(r.k * r.k, 0.0);
+        double A[KMAX * KMAX] = {0.0}, ev[KMAX];
         for (int e = 0; e < r.l; ++e) {
             const int a = r.edges[2 * e], b = r.edges[2 * e + 1];
             const double wgt = 1.0 / (r.cost[e] * r.cost[e]);
@@ -323,7 +320,8 @@ omt_status resolve(const omt_params *p, Resolved &r)
             A[a * r.k + b] -= wgt;
             A[b * r.k + a] -= wgt;
         }
-        r.lmax = jacobi_lambda_max(A, r.k);
+        jacobi_eigenvalues(A, r.k, ev);
+        for (int c = 0; c < r.k; ++c) r.lmax = std::max(r.lmax, ev[c]);
     }
     // step sizes of Sec. 7.1 / 7.2 unless given
     const double h2 = r.h * r.h;
@@ -335,7 +333,6 @@ omt_status resolve(const omt_params *p, Resolved &r)
             return fail(OMT_ESTEP, "tau mu 8/h^2 + tau nu lambda_max = %g must be < 1 (Sec. 7.2)", cond);
     }
     // mass classes: connected components of the channel graph
-    r.cls.resize(r.k);
     for (int c = 0; c < r.k; ++c) r.cls[c] = c;
     for (bool ch = true; ch;) {
         ch = false;
@@ -348,7 +345,8 @@ omt_status resolve(const omt_params *p, Resolved &r)
             }
         }
     }
-    std::vector<int> map(r.k, -1);
+    int map[KMAX];
+    for (int c = 0; c < r.k; ++c) map[c] = -1;
     r.ncls = 0;
     for (int c = 0; c < r.k; ++c) {
         if (map[r.cls[c]] < 0) map[r.cls[c]] = r.ncls++;
@@ -813,6 +811,100 @@ omt_status graph_interval(omt_ctx *h, int K, int T, int rowsT, int rows1)
 
 omt_status create_resolved(const Resolved &r, const void *rho0, const void *rho1, void *workspace, size_t ws_bytes,
                            void *stream, omt_handle *out);
+omt_status setup_ctx(omt_ctx *h, const Resolved &r, const void *rho0, const void *rho1, void *workspace,
+                     size_t ws_bytes, void *stream);
+
+// The iterations of omt_solve: intervals of check_every iterations, each
+// ending with the check of Sec. 6.1; full intervals are replayed as HIP
+// graphs when allow_graph is set (graphs allocate when first captured).
+omt_status solve_ctx(omt_ctx *h, int64_t max_iters, double tol, int32_t check_every, omt_info *info,
+                     bool allow_graph)
+{
+    if (max_iters < 0) return fail(OMT_EINVAL, "max_iters < 0");
+    const int K = check_every > 0 ? check_every : 64;
+    const int T = tblock_of(h);
+    omt_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    omt_status s = OMT_OK;
+    int64_t it = 0;
+    const int rowsT = default_rows(h, T), rows1 = default_rows(h, 1);
+    const bool use_graph = allow_graph && K >= 8;
+    if (use_graph) HIP_TRY(hipStreamSynchronize(h->stream));
+    while (it < max_iters) {
+        const int64_t nblk = std::min<int64_t>(K, max_iters - it);
+        if (use_graph && nblk == K) {
+            if ((s = graph_interval(h, K, T, rowsT, rows1)) != OMT_OK) return s;
+        } else {
+            if ((s = enqueue_interval(h, nblk, T, rowsT, rows1, h->stream)) != OMT_OK) return s;
+            if ((s = read_results(h, NMET)) != OMT_OK) return s;
+        }
+        it += nblk;
+        fill_info(h, h->host, &inf);
+        inf.iters = it;
+        inf.checks += 1;
+        if (!std::isfinite(inf.R) || !std::isfinite(inf.primal)) {
+            h->last = inf;
+            h->have_last = true;
+            if (info) *info = inf;
+            return fail(OMT_EDIVERGED, "non-finite residual after %lld iterations", (long long)it);
+        }
+        // same test as the batched kernel: R <= tol^2 R0
+        if (tol > 0.0 && inf.R <= tol * tol * (h->r.tau * h->fnorm2)) {
+            inf.converged = 1;
+            break;
+        }
+    }
+    h->last = inf;
+    h->have_last = true;
+    if (info) *info = inf;
+    if (tol > 0.0 && !inf.converged) return fail(OMT_ENOTCONV, "residual %.3g > tol %.3g after %lld iterations",
+                                                  inf.residual, tol, (long long)it);
+    return OMT_OK;
+}
+
+// ------------------------------------------------ static workspace
+//
+// omt_solve_static runs with its device workspace in `scratch`, a fixed
+// array of the library's code object: the loader gives every GPU its own
+// copy when the library first runs there, and it stays until the process
+// ends.  Host code never uses the array's name as an address (in host code
+// it stands for a host-side shadow): the device address of the current
+// GPU's copy comes from hipGetSymbolAddress, once per device, and only that
+// address is handed to kernels.
+#ifndef OMT_STATIC_WORKSPACE_BYTES
+#define OMT_STATIC_WORKSPACE_BYTES (64u << 20)
+#endif
+static_assert(OMT_STATIC_WORKSPACE_BYTES % 256 == 0, "static workspace keeps 256-byte alignment");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[OMT_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[STATIC_MAX_DEVICES];
+
+// Device address of the current GPU's copy of `scratch`.
+omt_status static_workspace(void **ptr)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES)
+        return fail(OMT_EUNSUPPORTED, "device %d: the static workspace serves devices 0..%d", dev,
+                    STATIC_MAX_DEVICES - 1);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(OMT_EDEVICE, "device %d: address of the static workspace: %s", dev, hipGetErrorString(e));
+        g_static_ptr[dev] = p;
+    }
+    *ptr = g_static_ptr[dev];
+    return OMT_OK;
+}
 
 }  // namespace
 
@@ -873,6 +965,29 @@ namespace {
 omt_status create_resolved(const Resolved &r, const void *rho0, const void *rho1, void *workspace, size_t ws_bytes,
                            void *stream, omt_handle *out)
 {
+    omt_ctx *h = new omt_ctx();
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->host), sizeof(double) * 64, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(OMT_EDEVICE, "set-up: %s", hipGetErrorString(e));
+    }
+    omt_status s = setup_ctx(h, r, rho0, rho1, workspace, ws_bytes, stream);
+    if (s != OMT_OK) {
+        (void)hipHostFree(h->host);
+        delete h;
+        return s;
+    }
+    tune_cache_load(h);
+    *out = h;
+    return OMT_OK;
+}
+
+// Everything omt_create does on the device, into a context whose host
+// buffer (64 doubles) the caller provides: mass check per class, f = rho1 -
+// rho0 minus the class mean, zero state, ||f||^2.  Allocates nothing.
+omt_status setup_ctx(omt_ctx *h, const Resolved &r, const void *rho0, const void *rho1, void *workspace,
+                     size_t ws_bytes, void *stream)
+{
     omt_status s = OMT_OK;
     if (!rho0 || !rho1) return fail(OMT_EINVAL, "rho0 / rho1 is NULL");
     if (!workspace) return fail(OMT_EINVAL, "workspace is NULL");
@@ -880,7 +995,6 @@ omt_status create_resolved(const Resolved &r, const void *rho0, const void *rho1
     const Layout L = make_layout(r);
     if (ws_bytes < L.total) return fail(OMT_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
 
-    omt_ctx *h = new omt_ctx();
     h->r = r;
     h->L = L;
     h->stream = static_cast<hipStream_t>(stream);
@@ -900,14 +1014,8 @@ omt_status create_resolved(const Resolved &r, const void *rho0, const void *rho1
     h->have_last = false;
     const int64_t npix = (int64_t)r.m * r.n;
     h->metric_blocks = int(std::min<int64_t>(METRIC_BLOCKS_MAX, (npix + 255) / 256));
-    auto bail = [&](omt_status st) {
-        if (h->host) (void)hipHostFree(h->host);
-        delete h;
-        return st;
-    };
     hipError_t e = hipGetDevice(&h->device);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&h->host), sizeof(double) * 64, hipHostMallocDefault);
-    if (e != hipSuccess) return bail(fail(OMT_EDEVICE, "set-up: %s", hipGetErrorString(e)));
+    if (e != hipSuccess) return fail(OMT_EDEVICE, "set-up: %s", hipGetErrorString(e));
 
     // FP64 per-channel masses and non-finite count of the inputs
     SumsArgs sa;
@@ -923,10 +1031,11 @@ omt_status create_resolved(const Resolved &r, const void *rho0, const void *rho1
     if (e == hipSuccess) e = launch_reduce_rows(h->part, sa.nblocks, W, h->res, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h->host, h->res, sizeof(double) * W, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return bail(fail(OMT_EDEVICE, "mass check: %s", hipGetErrorString(e)));
-    std::vector<double> sums(h->host, h->host + W);
-    if (sums[4 * r.k] > 0.0) return bail(fail(OMT_EINVAL, "%.0f non-finite input values", sums[4 * r.k]));
-    std::vector<double> s0(r.ncls, 0.0), s1(r.ncls, 0.0), a0(r.ncls, 0.0), a1(r.ncls, 0.0), cnt(r.ncls, 0.0);
+    if (e != hipSuccess) return fail(OMT_EDEVICE, "mass check: %s", hipGetErrorString(e));
+    double sums[4 * KMAX + 1];
+    std::memcpy(sums, h->host, sizeof(double) * W);
+    if (sums[4 * r.k] > 0.0) return fail(OMT_EINVAL, "%.0f non-finite input values", sums[4 * r.k]);
+    double s0[KMAX] = {0.0}, s1[KMAX] = {0.0}, a0[KMAX] = {0.0}, a1[KMAX] = {0.0}, cnt[KMAX] = {0.0};
     for (int c = 0; c < r.k; ++c) {
         const int g = r.cls[c];
         if (g < 0) continue;
@@ -940,8 +1049,8 @@ omt_status create_resolved(const Resolved &r, const void *rho0, const void *rho1
         const double den = std::max(a0[g], a1[g]);
         const double rel = den > 0.0 ? std::fabs(s0[g] - s1[g]) / den : 0.0;
         if (rel > 1e-6)
-            return bail(fail(OMT_EMASS, "mass class %d: sum rho0 = %.9g, sum rho1 = %.9g (relative %.3g > 1e-6)", g,
-                             s0[g], s1[g], rel));
+            return fail(OMT_EMASS, "mass class %d: sum rho0 = %.9g, sum rho1 = %.9g (relative %.3g > 1e-6)", g,
+                        s0[g], s1[g], rel);
     }
     for (int c = 0; c < r.k; ++c) h->host[c] = r.cls[c] < 0 ? 0.0 : (s1[r.cls[c]] - s0[r.cls[c]]) / cnt[r.cls[c]];
     e = hipMemcpyAsync(h->vec, h->host, sizeof(double) * r.k, hipMemcpyHostToDevice, h->stream);
@@ -959,14 +1068,12 @@ omt_status create_resolved(const Resolved &r, const void *rho0, const void *rho1
     fa.f = h->f;
     if (e == hipSuccess) e = launch_zero(h->ws, L.off_part, h->stream);
     if (e == hipSuccess) e = launch_make_f(fa, h->stream);
-    if (e != hipSuccess) return bail(fail(OMT_EDEVICE, "set-up: %s", hipGetErrorString(e)));
+    if (e != hipSuccess) return fail(OMT_EDEVICE, "set-up: %s", hipGetErrorString(e));
     // ||f||^2 from the objectives of the zero state
     s = run_metrics(h, 0, 0, 0, 0);
     if (s == OMT_OK) s = read_results(h, NMET);
-    if (s != OMT_OK) return bail(s);
+    if (s != OMT_OK) return s;
     h->fnorm2 = h->host[6];
-    tune_cache_load(h);
-    *out = h;
     return OMT_OK;
 }
 
@@ -977,47 +1084,8 @@ extern "C" {
 omt_status omt_solve(omt_handle h, int64_t max_iters, double tol, int32_t check_every, omt_info *info)
 {
     if (!h) return fail(OMT_EINVAL, "handle is NULL");
-    if (max_iters < 0) return fail(OMT_EINVAL, "max_iters < 0");
-    const int K = check_every > 0 ? check_every : 64;
-    const int T = tblock_of(h);
-    omt_info inf;
-    std::memset(&inf, 0, sizeof(inf));
-    omt_status s = OMT_OK;
-    int64_t it = 0;
-    const int rowsT = default_rows(h, T), rows1 = default_rows(h, 1);
     // full intervals are replayed as graphs unless OMT_NO_GRAPH is set
-    const bool use_graph = K >= 8 && !std::getenv("OMT_NO_GRAPH");
-    if (use_graph) HIP_TRY(hipStreamSynchronize(h->stream));
-    while (it < max_iters) {
-        const int64_t nblk = std::min<int64_t>(K, max_iters - it);
-        if (use_graph && nblk == K) {
-            if ((s = graph_interval(h, K, T, rowsT, rows1)) != OMT_OK) return s;
-        } else {
-            if ((s = enqueue_interval(h, nblk, T, rowsT, rows1, h->stream)) != OMT_OK) return s;
-            if ((s = read_results(h, NMET)) != OMT_OK) return s;
-        }
-        it += nblk;
-        fill_info(h, h->host, &inf);
-        inf.iters = it;
-        inf.checks += 1;
-        if (!std::isfinite(inf.R) || !std::isfinite(inf.primal)) {
-            h->last = inf;
-            h->have_last = true;
-            if (info) *info = inf;
-            return fail(OMT_EDIVERGED, "non-finite residual after %lld iterations", (long long)it);
-        }
-        // same test as the batched kernel: R <= tol^2 R0
-        if (tol > 0.0 && inf.R <= tol * tol * (h->r.tau * h->fnorm2)) {
-            inf.converged = 1;
-            break;
-        }
-    }
-    h->last = inf;
-    h->have_last = true;
-    if (info) *info = inf;
-    if (tol > 0.0 && !inf.converged) return fail(OMT_ENOTCONV, "residual %.3g > tol %.3g after %lld iterations",
-                                                  inf.residual, tol, (long long)it);
-    return OMT_OK;
+    return solve_ctx(h, max_iters, tol, check_every, info, !std::getenv("OMT_NO_GRAPH"));
 }
 
 omt_status omt_distance(omt_handle h, double *V, omt_info *info)
@@ -1060,7 +1128,7 @@ omt_status omt_grad(omt_handle h, void *d_rho0, void *d_rho1)
     HIP_TRY(launch_reduce_rows(h->part, pa.nblocks, r.k, h->res, h->stream));
     omt_status s = read_results(h, r.k);
     if (s != OMT_OK) return s;
-    std::vector<double> cs(r.ncls, 0.0), cn(r.ncls, 0.0);
+    double cs[KMAX] = {0.0}, cn[KMAX] = {0.0};
     for (int c = 0; c < r.k; ++c) {
         if (r.cls[c] < 0) continue;
         cs[r.cls[c]] += h->host[c];
@@ -1199,6 +1267,33 @@ omt_status omt_time_steps(omt_handle h, int32_t T, int32_t rows_per_wave, int64_
     h->have_last = false;
     if (us_per_launch) *us_per_launch = 1000.0 * double(ms) / double(n / T);
     return OMT_OK;
+}
+
+omt_status omt_solve_static(const omt_params *p, const void *rho0, const void *rho1, int64_t max_iters, double tol,
+                            int32_t check_every, double *V, void *d_rho0, void *d_rho1, omt_info *info, void *stream)
+{
+    Resolved r;
+    omt_status s = resolve(p, r);
+    if (s != OMT_OK) return s;
+    if (max_iters < 0) return fail(OMT_EINVAL, "max_iters < 0");
+    const size_t need = make_layout(r).total;
+    if (need > size_t(OMT_STATIC_WORKSPACE_BYTES))
+        return fail(OMT_ENOMEM, "the problem needs %zu bytes of device workspace; the static workspace holds %zu",
+                    need, size_t(OMT_STATIC_WORKSPACE_BYTES));
+    void *ws = nullptr;
+    if ((s = static_workspace(&ws)) != OMT_OK) return s;
+    // a context on the stack with a pageable host buffer: no graph, stream,
+    // pinned or device memory belongs to it, so nothing is released after
+    omt_ctx h{};
+    double host[64];
+    h.host = host;
+    if ((s = setup_ctx(&h, r, rho0, rho1, ws, need, stream)) != OMT_OK) return s;
+    const omt_status sv = solve_ctx(&h, max_iters, tol, check_every, info, false);
+    if (sv != OMT_OK && sv != OMT_ENOTCONV) return sv;
+    if (V && (s = omt_distance(&h, V, nullptr)) != OMT_OK) return s;
+    if ((d_rho0 || d_rho1) && (s = omt_grad(&h, d_rho0, d_rho1)) != OMT_OK) return s;
+    if (!V && !d_rho0 && !d_rho1) HIP_TRY(hipStreamSynchronize(h.stream));
+    return sv;
 }
 
 omt_status omt_autotune(omt_handle h, int32_t iters_per_trial, int32_t *best_t, int32_t *best_rows, double *best_us)
@@ -1365,7 +1460,7 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
     for (int p = 0; p < B; ++p) {
         Resolved r;
         omt_status s = resolve(&params[p], r);
-        if (s != OMT_OK) return fail(s, "problem %d: %s", p, g_last_error.c_str());
+        if (s != OMT_OK) return fail(s, "problem %d: %s", p, g_last_error);
         if (p == 0) *dtype = r.dtype;
         if (r.dtype != *dtype) return fail(OMT_EINVAL, "problem %d: all problems of a batch must share the dtype", p);
         if (batch_type(r.k, r.gk, r.lb) < 0)
@@ -1624,9 +1719,10 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         omt_ctx *c = nullptr;
         s = omt_create(&params[p], rho0[p], rho1[p], h->ws + L.off[p], L.bytes[p], stream, &c);
         if (s != OMT_OK) {
-            std::string why = g_last_error;
+            char why[sizeof(g_last_error)];
+            std::memcpy(why, g_last_error, sizeof(why));
             destroy_batch(h);
-            return fail(s, "problem %d: %s", p, why.c_str());
+            return fail(s, "problem %d: %s", p, why);
         }
         h->ctx.push_back(c);
     }
@@ -1815,7 +1911,7 @@ const char *omt_strerror(omt_status s)
     }
 }
 
-const char *omt_last_error(void) { return g_last_error.c_str(); }
+const char *omt_last_error(void) { return g_last_error; }
 
 int32_t omt_version(void) { return 1; }
 
@@ -1963,7 +2059,8 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
             for (int e = 0; e < fl; ++e) v += Gf[size_t(e) * fK + a] * Gf[size_t(e) * fK + b];
             A[a * fK + b] = v;
         }
-    const std::vector<double> ev = jacobi_eigenvalues(A, fK);
+    std::vector<double> ev(fK);
+    jacobi_eigenvalues(A.data(), fK, ev.data());
     double lmax = 0.0;
     for (double v : ev) lmax = std::max(lmax, v);
     int nker = 0;
@@ -2016,7 +2113,7 @@ omt_status resolve_matrix(const omt_matrix_params *p, Resolved &r, MatrixSpec &m
             r.wwt[s * ms.Ks + q] = q < snd ? 1.0 : (real || (q - snd) % 2 == 0 ? std::sqrt(2.0) : 0.0);
     // mass: only the trace is conserved; the diagonal coordinates form the
     // one class whose mean is removed
-    r.cls.assign(ms.K, -1);
+    for (int c = 0; c < ms.K; ++c) r.cls[c] = -1;
     for (int c = 0; c < nd; ++c) r.cls[c] = 0;
     r.ncls = 1;
     if (!fields_fit(r))

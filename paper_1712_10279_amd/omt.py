@@ -87,6 +87,8 @@ _SIGS = {
     "omt_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]),
     "omt_time_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_double)]),
+    "omt_solve_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32,
+                                   C.POINTER(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "omt_matrix_params_init": (C.c_int, [C.POINTER(MatrixParams)]),
     "omt_matrix_resolve": (C.c_int, [C.POINTER(MatrixParams)] + [C.POINTER(C.c_double)] * 4 +
                            [C.POINTER(C.c_int32)] * 2),
@@ -282,6 +284,34 @@ def distance(rho0, rho1, edges=None, max_iters=10000, tol=0.0, check_every=64, *
     s = Solver(rho0, rho1, edges, **kw)
     s.solve(max_iters, tol, check_every)
     return s.distance()[0]
+
+
+def solve_static(rho0, rho1, edges=None, max_iters=10000, tol=0.0, check_every=64, d_rho0=None, d_rho1=None,
+                 allow_notconv=True, **kw):
+    """One whole solve through omt_solve_static (device workspace inside the
+    library; the call allocates nothing).  d_rho0 / d_rho1: optional output
+    tensors (m, n, k) of the input dtype on the same device, filled with
+    Phi and -Phi.  Returns (V, info)."""
+    torch = _torch()
+    if rho0.dim() != 3 or rho0.shape != rho1.shape or rho0.dtype != rho1.dtype:
+        raise ValueError("rho0 and rho1 must both be (m, n, k) of one dtype")
+    if not (rho0.is_cuda and rho1.is_cuda):
+        raise ValueError("rho0 and rho1 must be on the GPU")
+    for t in (d_rho0, d_rho1):
+        if t is not None and (t.shape != rho0.shape or t.dtype != rho0.dtype or not t.is_contiguous()):
+            raise ValueError("outputs must be contiguous tensors shaped and typed like rho0")
+    m, n, k = (int(x) for x in rho0.shape)
+    e = np.zeros((0, 2), np.int32) if edges is None else np.asarray(edges, np.int32).reshape(-1, 2)
+    dt = F64 if rho0.dtype == torch.float64 else F32
+    p, keep = make_params(m, n, k, e, Config(**kw), dt)
+    r0, r1 = rho0.contiguous(), rho1.contiguous()
+    V = C.c_double()
+    info = Info()
+    allow = (ENOTCONV,) if allow_notconv else ()
+    _check(lib().omt_solve_static(C.byref(p), _ptr(r0), _ptr(r1), int(max_iters), float(tol), int(check_every),
+                                  C.byref(V), _ptr(d_rho0), _ptr(d_rho1), C.byref(info), _stream_ptr()),
+           "omt_solve_static", allow)
+    return V.value, info.as_dict()
 
 
 # ----------------------------------------------------------------- autograd

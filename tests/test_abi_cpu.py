@@ -151,3 +151,17 @@ def test_matrix_two_iterations_per_pass_accepted():
     for L, real in ((L_DTI, True), (np.stack([PAULI["x"], PAULI["z"]]), False)):
         for unorm, wnorm in ((omt.M_FRO, omt.M_L1), (omt.M_L1, omt.M_FRO)):
             omt.matrix_resolve(12, 12, L, real, tblock=2, unorm=unorm, wnorm=wnorm)
+
+
+def test_static_entry_rejects_oversize_before_device_work():
+    """omt_solve_static refuses a problem beyond its fixed workspace with
+    OMT_ENOMEM before touching the device (so this runs without a GPU)."""
+    import ctypes as C
+    p, keep = omt.make_params(1024, 1024, 3, [(0, 1), (0, 2), (1, 2)], omt.Config(), omt.F32)
+    need = omt.workspace_bytes(1024, 1024, 3, [(0, 1), (0, 2), (1, 2)])
+    assert need > 64 << 20
+    st = omt.lib().omt_solve_static(C.byref(p), None, None, 10, 0.0, 64, None, None, None, None, None)
+    assert st == omt.ENOMEM
+    assert b"static workspace" in omt.lib().omt_last_error()
+    p.k = 0
+    assert omt.lib().omt_solve_static(C.byref(p), None, None, 10, 0.0, 64, None, None, None, None, None) == omt.EINVAL
