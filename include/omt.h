@@ -201,6 +201,9 @@ omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, in
 omt_status omt_batch_distance(omt_batch_handle h, double *V /* host, B */);
 omt_status omt_batch_grad(omt_batch_handle h, void *const *d_rho0, void *const *d_rho1);
 omt_status omt_batch_get_state(omt_batch_handle h, int32_t b, void *phi, void *u, void *w);
+/* Warm start of problem b of the batch (as omt_set_state; Sec. 7.2 takes
+ * initial guesses); the next omt_batch_solve continues from it. */
+omt_status omt_batch_set_state(omt_batch_handle h, int32_t b, const void *phi, const void *u, const void *w);
 omt_status omt_batch_destroy(omt_batch_handle h);
 
 /* ----------------------------------------------------------- utilities */

@@ -134,6 +134,24 @@ __global__ __launch_bounds__(WAVE) void reduce_tiles_kernel(const double *partia
     dev::reduce_tiles(partials, 0, ntiles, threadIdx.x, out);
 }
 
+// One wave per (row block, four column tiles): lanes 16 u .. 16 u + 15 hold
+// the quads of tile 4 x + u and add them with shuffle offsets 1, 2, 4, 8
+// (the last four levels of wave_sum); quads past the grid count as zero.
+__global__ __launch_bounds__(WAVE) void quads_to_tiles_kernel(const double *qpart, int64_t qstride, int nq, int ncolw,
+                                                              double *partials)
+{
+    const int blk = blockIdx.y;
+    const int tile = blockIdx.x * 4 + int(threadIdx.x) / 16;
+    const int quad = tile * 16 + int(threadIdx.x) % 16;
+    const bool ok = tile < ncolw && quad < nq;
+    for (int q = 0; q < NMET; ++q) {
+        double x = ok ? qpart[q * qstride + (int64_t)blk * nq + quad] : 0.0;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) x += __shfl_down(x, off, WAVE);
+        if (threadIdx.x % 16 == 0 && tile < ncolw) partials[((int64_t)blk * ncolw + tile) * NMET + q] = x;
+    }
+}
+
 __global__ __launch_bounds__(RB) void plane_sums_kernel(PlaneSumArgs a)
 {
     for (int c = 0; c < a.k; ++c) {
@@ -282,6 +300,14 @@ hipError_t launch_reduce_rows(const double *partials, int nblocks, int width, do
 hipError_t launch_reduce_tiles(const double *partials, int ntiles, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(reduce_tiles_kernel, dim3(1), dim3(WAVE), 0, s, partials, ntiles, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_quads_to_tiles(const double *qpart, int64_t qstride, int nq, int nblk, int ncolw, double *partials,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(quads_to_tiles_kernel, dim3(unsigned((ncolw + 3) / 4), unsigned(nblk)), dim3(WAVE), 0, s, qpart,
+                       qstride, nq, ncolw, partials);
     return hipGetLastError();
 }
 

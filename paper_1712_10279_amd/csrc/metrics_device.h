@@ -11,8 +11,13 @@
 //   v[5] = <phi', f>                                         (dual objective)
 //   v[6] = |div_x u' + div_G w' + f|^2                       (constraint residual)
 //   v[7] = sum of phi'
-// A tile is 64 aligned columns by MET_ROWS rows; each wave sums one tile and
-// a single wave adds the tiles of a problem in tile order.
+// The terms of a pixel are formed by chan_terms / pixel_terms (step_device.h)
+// in a fixed order.  A tile is 64 aligned columns by MET_ROWS rows: each lane
+// adds its column's pixels row by row, the wave adds its lanes with
+// wave_sum (neighbours first), and a single wave adds the tiles of a problem
+// in tile order.  A check fused into a single-iteration step launch forms
+// the same column and quad sums in registers and quads_to_tiles the same
+// tiles, so both ways of taking a check give identical values.
 #pragma once
 
 #include "step_device.h"
@@ -80,7 +85,6 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
                 p0 += double(ld_field(&a.plo_in[c * P + o]));
                 p1 += double(ld_field(&a.plo_out[c * P + o]));
             }
-            const double dp = p1 - p0;
             const double lx0 = double(ld_field(&u0[c * P + o])), lx1 = double(ld_field(&u1[c * P + o]));
             const double ly0 = double(ld_field(&u0[(K + c) * P + o])), ly1 = double(ld_field(&u1[(K + c) * P + o]));
             const double lxl0 = double(ld_field(&u0[c * P + oi])), lxl1 = double(ld_field(&u1[c * P + oi]));
@@ -90,38 +94,10 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
             const double uy0 = j < a.n - 1 ? ly0 : 0.0, uy1 = j < a.n - 1 ? ly1 : 0.0;
             const double xl0 = i > 0 ? lxl0 : 0.0, xl1 = i > 0 ? lxl1 : 0.0;
             const double yl0 = j > 0 ? lyl0 : 0.0, yl1 = j > 0 ? lyl1 : 0.0;
-            const double dux = ux1 - ux0, duy = uy1 - uy0;
-            const double ddiv = ((dux - (xl1 - xl0)) + duy - (yl1 - yl0)) * inv_h;
-            const double div1 = ((ux1 - xl1) + uy1 - yl1) * inv_h;
-            // D diag(1/c) applied to w' - w and to w' (div_G is its negative)
             double dgd = 0.0, dg1 = 0.0;
-            if constexpr (L > 0) {
-#pragma unroll
-                for (int e = 0; e < LA; ++e) {
-                    if constexpr (GK == G_DENSE || is_matrix_kind(GK)) {
-                        dgd += double(a.gm[c * LMAX + e]) * (we1[e] - we0[e]);
-                        dg1 += double(a.gm[c * LMAX + e]) * we1[e];
-                    } else {
-                        if (edge_a<GK, K>(e) == c) {
-                            dgd += double(a.ic[e]) * (we1[e] - we0[e]);
-                            dg1 += double(a.ic[e]) * we1[e];
-                        }
-                        if (edge_b<GK, K>(e) == c) {
-                            dgd -= double(a.ic[e]) * (we1[e] - we0[e]);
-                            dg1 -= double(a.ic[e]) * we1[e];
-                        }
-                    }
-                }
-            }
+            if constexpr (L > 0) graph_div_terms<R, K, GK, LA>(a, c, we0, we1, dgd, dg1);
             const double fc = double(ld_field(&a.f[c * P + o]));
-            acc[0] += dux * dux + duy * duy;
-            acc[2] += dp * dp;
-            acc[3] += dp * (ddiv - dgd);
-            acc[5] += p1 * fc;
-            const double r = (div1 - dg1) + fc;
-            acc[6] += r * r;
-            acc[7] += p1;
-            sq += ux1 * ux1 + uy1 * uy1;
+            chan_terms(acc, sq, u2, a.unorm, inv_h, p0, p1, ux0, ux1, uy0, uy1, xl0, xl1, yl0, yl1, dgd, dg1, fc);
             if constexpr (is_matrix_kind(GK)) {
                 if (a.unorm == 3) {
                     const double wc = double(a.uwt[c]);
@@ -139,53 +115,42 @@ __device__ __forceinline__ void tile_metrics(const StepArgs<R> &a, int wc, int w
                     }
                 }
             }
-            if (a.unorm == 0)
-                acc[4] += sqrt(ux1 * ux1 + uy1 * uy1);
-            else if (a.unorm == 1)
-                acc[4] += fabs(ux1) + fabs(uy1);
-            else
-                u2 += ux1 * ux1 + uy1 * uy1;
         }
-        if (a.unorm == 2) acc[4] += sqrt(u2);
-        if constexpr (GK == G_MATNUC) {
-            if (a.unorm == 4) {  // nuclear norm of each direction of u'
-                double cx[K], cy[K];
+        if constexpr (is_matrix_kind(GK)) {
+            if (a.unorm == 2) acc[4] += sqrt(u2);
+            if constexpr (GK == G_MATNUC) {
+                if (a.unorm == 4) {  // nuclear norm of each direction of u'
+                    double cx[K], cy[K];
 #pragma unroll
-                for (int c = 0; c < K; ++c) {
-                    const double vx = double(ld_field(&u1[c * P + o])), vy = double(ld_field(&u1[(K + c) * P + o]));
-                    cx[c] = i < a.m - 1 ? vx : 0.0;
-                    cy[c] = j < a.n - 1 ? vy : 0.0;
+                    for (int c = 0; c < K; ++c) {
+                        const double vx = double(ld_field(&u1[c * P + o])), vy = double(ld_field(&u1[(K + c) * P + o]));
+                        cx[c] = i < a.m - 1 ? vx : 0.0;
+                        cy[c] = j < a.n - 1 ? vy : 0.0;
+                    }
+                    acc[4] += herm_nuc<double, K>(cx) + herm_nuc<double, K>(cy);
                 }
-                acc[4] += herm_nuc<double, K>(cx) + herm_nuc<double, K>(cy);
             }
-        }
-
-        double wn = 0.0, w2 = 0.0;
+            double wn = 0.0, w2 = 0.0;
 #pragma unroll
-        for (int e = 0; e < LA; ++e) {
-            acc[1] += (we1[e] - we0[e]) * (we1[e] - we0[e]);
-            wn += fabs(we1[e]);
-            w2 += we1[e] * we1[e];
+            for (int e = 0; e < LA; ++e) {
+                acc[1] += (we1[e] - we0[e]) * (we1[e] - we0[e]);
+                wn += fabs(we1[e]);
+                w2 += we1[e] * we1[e];
+            }
+            if (a.wnorm == 2)
+                acc[4] += a.alpha * group_norm<LA>(a.wwt, we1);
+            else if (GK == G_MATNUC && a.wnorm == 3)
+                acc[4] += a.alpha * skew_nuc<K, LA>(we1, a.l);
+            else
+                acc[4] += a.alpha * (a.wnorm == 0 ? wn : sqrt(w2));
+            if (a.eps > 0.0) acc[4] += a.eps * (sq + w2);
+        } else {
+            pixel_terms<LA>(acc, sq, u2, a.unorm, a.wnorm, a.alpha, a.eps, L > 0 ? a.l : 0, we0, we1);
         }
-        if (is_matrix_kind(GK) && a.wnorm == 2)
-            acc[4] += a.alpha * group_norm<LA>(a.wwt, we1);
-        else if (GK == G_MATNUC && a.wnorm == 3)
-            acc[4] += a.alpha * skew_nuc<K, LA>(we1, a.l);
-        else
-            acc[4] += a.alpha * (a.wnorm == 0 ? wn : sqrt(w2));
-        if (a.eps > 0.0) acc[4] += a.eps * (sq + w2);  // quadratic regularisation
         // lanes past the grid add nothing (their terms are dropped as a whole)
 #pragma unroll
         for (int q = 0; q < NMET; ++q) v[q] += jok ? acc[q] : 0.0;
     }
-}
-
-// Sum over the 64 lanes of a wave (fixed tree); lane 0 holds the result.
-__device__ __forceinline__ double wave_sum(double x)
-{
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) x += __shfl_down(x, off, WAVE);
-    return x;
 }
 
 // One wave: out[q] = sum over tiles t0..t0+nt-1 of partials[t][q], in a fixed
@@ -198,6 +163,9 @@ __device__ __forceinline__ void reduce_tiles(const double *partials, int t0, int
     double s[NMET];
 #pragma unroll
     for (int q = 0; q < NMET; ++q) s[q] = 0.0;
+    // unrolled so that the loads of several tiles are in flight at once;
+    // every sum still takes its tiles one after another in increasing order
+#pragma unroll 4
     for (int t = lane; t < nt; t += WAVE) {
         const double *row = partials + (int64_t)(t0 + t) * NMET;
 #pragma unroll

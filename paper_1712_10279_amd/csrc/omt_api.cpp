@@ -369,7 +369,9 @@ struct Layout {
     int pitch;
     int64_t plane;  // elements
     size_t esz;
-    size_t off_f, off_phi[2], off_u[2], off_w[2], off_plo[2], off_part, off_res, off_vec, total;
+    size_t off_f, off_phi[2], off_u[2], off_w[2], off_plo[2], off_part, off_quad, off_res, off_vec, total;
+    int64_t qstride;  // doubles per quantity of the quad sums of a check launch
+    int nq, nqb;      // quads (4 columns) per row, row blocks (MET_ROWS rows)
 };
 
 Layout make_layout(const Resolved &r)
@@ -404,6 +406,11 @@ Layout make_layout(const Resolved &r)
     size_t npart = std::max<size_t>(size_t(METRIC_BLOCKS_MAX) * KMAX, size_t(SUM_BLOCKS_MAX) * (4 * KMAX + 1));
     npart = std::max(npart, met_tiles * NMET);
     o += align256(sizeof(double) * npart);
+    L.nq = (r.n + 3) / 4;
+    L.nqb = (r.m + MET_ROWS - 1) / MET_ROWS;
+    L.qstride = int64_t(L.nq) * L.nqb;
+    L.off_quad = o;
+    o += align256(sizeof(double) * NMET * size_t(L.qstride));
     L.off_res = o;
     o += align256(sizeof(double) * 64);
     L.off_vec = o;
@@ -424,7 +431,7 @@ struct omt_ctx {
     char *ws;
     void *f, *phi[2], *u[2], *w[2];
     float *plo[2];
-    double *part, *res, *vec;
+    double *part, *quad, *res, *vec;
     double *host;  // pinned, 64 doubles
     int cur, wcur;
     double fnorm2;
@@ -481,6 +488,9 @@ void fill_args(StepArgs<R> &a, const omt_ctx *h, int ci, int co, int wi, int wo,
     a.eps = r.eps;
     a.ureg = R(1.0 / (1.0 + 2.0 * r.mu * r.eps));
     a.wreg = R(1.0 / (1.0 + 2.0 * r.nu * r.eps));
+    a.qpart = h->quad;
+    a.qstride = h->L.qstride;
+    a.nq = h->L.nq;
     for (int q = 0; q < KMAX * LMAX; ++q) a.gm[q] = R(0);
     for (int q = 0; q < LMAX; ++q) a.ic[q] = R(0);
     for (int q = 0; q < KMAX; ++q) a.uwt[q] = R(1);
@@ -542,7 +552,9 @@ int rule_rows(const omt_ctx *h, int T)
 }
 
 // One launch advancing T iterations.  w is updated in place when allowed.
-omt_status step_launch(omt_ctx *h, int T, int rows, bool w_inplace, hipStream_t stream = nullptr)
+// check: the launch also takes the check of its last iteration (its quad
+// sums go to h->quad; rows must then be a multiple of MET_ROWS).
+omt_status step_launch(omt_ctx *h, int T, int rows, bool w_inplace, hipStream_t stream = nullptr, bool check = false)
 {
     if (!stream) stream = h->stream;
     const Resolved &r = h->r;
@@ -561,6 +573,7 @@ omt_status step_launch(omt_ctx *h, int T, int rows, bool w_inplace, hipStream_t 
     Lc.T = T;
     Lc.comp = r.comp;
     Lc.stream = stream;
+    Lc.check = check;
     hipError_t e;
     const int wo = w_inplace ? h->wcur : 1 - h->wcur;
     if (r.dtype == OMT_F64) {
@@ -730,9 +743,28 @@ void tune_cache_store(const omt_ctx *h, int T, int rows, double us)
     std::rename(tmp.c_str(), path);
 }
 
+// Rows per wave of a check launch: a multiple of MET_ROWS near the step's,
+// so that each aligned row block of the check sums lies in one wave.
+int check_rows(int rows) { return std::max(MET_ROWS, (rows + MET_ROWS / 2) / MET_ROWS * MET_ROWS); }
+
+// The single-iteration launch that also takes its check, then the check
+// sums reduced in a fixed order into h->res: quads to tiles to totals.
+omt_status check_launch(omt_ctx *h, int rows, hipStream_t stream)
+{
+    omt_status s = step_launch(h, 1, check_rows(rows), true, stream, true);
+    if (s != OMT_OK) return s;
+    const int ncolw = (h->r.n + WAVE - 1) / WAVE;
+    HIP_TRY(launch_quads_to_tiles(h->quad, h->L.qstride, h->L.nq, h->L.nqb, ncolw, h->part, stream));
+    HIP_TRY(launch_reduce_tiles(h->part, ncolw * h->L.nqb, h->res, stream));
+    return OMT_OK;
+}
+
 // Enqueue one check interval of nblk iterations on stream: nblk - 1
 // iterations T per launch while T fits, then single ones, then the checked
-// iteration (both iterates kept for R^k) and its metrics.
+// iteration (R^k needs its old and new iterates).  Vector problems take the
+// check inside that single-iteration launch (two-iteration launches with the
+// check measured slower: its registers leave one wave per SIMD); matrix
+// problems keep both iterates and run the separate metrics pass.
 omt_status enqueue_interval(omt_ctx *h, int64_t nblk, int T, int rowsT, int rows1, hipStream_t stream)
 {
     omt_status s;
@@ -745,6 +777,7 @@ omt_status enqueue_interval(omt_ctx *h, int64_t nblk, int T, int rowsT, int rows
         if ((s = step_launch(h, 1, rows1, true, stream)) != OMT_OK) return s;
         --rest;
     }
+    if (check_compiled(h->r.gk)) return check_launch(h, rows1, stream);
     const int oc = h->cur, ow = h->wcur;
     if ((s = step_launch(h, 1, rows1, false, stream)) != OMT_OK) return s;
     return run_metrics(h, oc, h->cur, ow, h->wcur, stream);
@@ -1007,6 +1040,7 @@ omt_status setup_ctx(omt_ctx *h, const Resolved &r, const void *rho0, const void
         h->plo[b] = r.comp ? reinterpret_cast<float *>(h->ws + L.off_plo[b]) : nullptr;
     }
     h->part = reinterpret_cast<double *>(h->ws + L.off_part);
+    h->quad = reinterpret_cast<double *>(h->ws + L.off_quad);
     h->res = reinterpret_cast<double *>(h->ws + L.off_res);
     h->vec = reinterpret_cast<double *>(h->ws + L.off_vec);
     h->cur = h->wcur = 0;
@@ -1886,6 +1920,15 @@ omt_status omt_batch_get_state(omt_batch_handle h, int32_t b, void *phi, void *u
     if (!h) return fail(OMT_EINVAL, "handle is NULL");
     if (b < 0 || b >= h->B) return fail(OMT_EINVAL, "problem index %d out of range", b);
     return omt_get_state(h->ctx[b], phi, u, w);
+}
+
+omt_status omt_batch_set_state(omt_batch_handle h, int32_t b, const void *phi, const void *u, const void *w)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    if (b < 0 || b >= h->B) return fail(OMT_EINVAL, "problem index %d out of range", b);
+    // the next omt_batch_solve builds its step arguments from the problem's
+    // current buffers, which this fills
+    return omt_set_state(h->ctx[b], phi, u, w);
 }
 
 omt_status omt_batch_destroy(omt_batch_handle h)

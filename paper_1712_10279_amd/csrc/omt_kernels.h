@@ -82,6 +82,11 @@ struct StepArgs {
     // coordinate; 0 marks the second coordinate of a two-coordinate group
     R uwt[KMAX];
     R wwt[LMAX];
+    // check launches: quad sums of the check terms, quantity q of row block
+    // b (MET_ROWS rows) and quad g (4 columns) at qpart[q * qstride + b * nq + g]
+    double *qpart;
+    int64_t qstride;
+    int32_t nq;
 };
 
 struct StepLaunch {
@@ -92,7 +97,12 @@ struct StepLaunch {
     bool comp;   // compensated potential
     const void *args;
     hipStream_t stream;
+    bool check = false;  // also take the check of the last iteration (args.qpart)
 };
+
+// Graph kinds whose step kernel can take the check in the same pass (the
+// vector method; the matrix kinds run the separate metrics pass).
+constexpr bool check_compiled(int gk) { return !is_matrix_kind(gk); }
 
 // Defined once per channel count in step.hip (compiled per channel count).
 hipError_t launch_step(const StepLaunch &L);
@@ -103,6 +113,11 @@ hipError_t step_blocks_per_cu(const StepLaunch &L, int *blocks);  // resident wo
 hipError_t launch_tile_metrics(const StepLaunch &L, int ncolw, int ntiles, double *partials);
 // out[q] = sum of the ntiles rows of partials (one wave, fixed order).
 hipError_t launch_reduce_tiles(const double *partials, int ntiles, double *out, hipStream_t s);
+// Tile rows [nblk * ncolw][NMET] (tile = block * ncolw + column tile) from the
+// quad sums a check launch stores (qpart[q * qstride + block * nq + quad]),
+// adding each tile's 16 quads as the last four levels of wave_sum do.
+hipError_t launch_quads_to_tiles(const double *qpart, int64_t qstride, int nq, int nblk, int ncolw, double *partials,
+                                 hipStream_t s);
 
 // ---------------------------------------------------------------- batched
 

@@ -37,7 +37,9 @@ namespace {
 
 using namespace dev;
 
-template <typename R, int K, int GK, int L, int T, bool COMP>
+// CHK: the launch also takes the check of its last iteration (Sec. 6.1),
+// writing quad sums of the check terms to a.qpart.
+template <typename R, int K, int GK, int L, int T, bool COMP, bool CHK>
 __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step_kernel(const StepArgs<R> a)
 {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -45,7 +47,7 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step_kernel(cons
     const int wc = g % a.ncolw;
     const int wr = (g / a.ncolw) * STEP_WAVES_PER_WG + (threadIdx.x / WAVE);
     if (wr >= a.nroww) return;  // whole wave leaves; no barriers follow
-    process_strip<R, K, GK, L, T, COMP>(a, wc, wr, lane);
+    process_strip<R, K, GK, L, T, COMP, CHK>(a, wc, wr, lane);
 }
 
 template <typename R, int K, int GK, int L, bool COMP>
@@ -70,15 +72,25 @@ template <typename R, int GK, int L, int T, bool COMP>
 hipError_t launch_one(const StepLaunch &Lc)
 {
     const StepArgs<R> &a = *static_cast<const StepArgs<R> *>(Lc.args);
-    hipLaunchKernelGGL((pdhg_step_kernel<R, OMT_K, GK, L, T, COMP>), dim3(a.nwg), dim3(WAVE * STEP_WAVES_PER_WG), 0,
-                       Lc.stream, a);
+    // the check is compiled into single-iteration launches of the vector method
+    if constexpr (check_compiled(GK) && T == 1) {
+        if (Lc.check) {
+            hipLaunchKernelGGL((pdhg_step_kernel<R, OMT_K, GK, L, T, COMP, true>), dim3(a.nwg),
+                               dim3(WAVE * STEP_WAVES_PER_WG), 0, Lc.stream, a);
+            return hipGetLastError();
+        }
+    } else {
+        if (Lc.check) return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((pdhg_step_kernel<R, OMT_K, GK, L, T, COMP, false>), dim3(a.nwg), dim3(WAVE * STEP_WAVES_PER_WG),
+                       0, Lc.stream, a);
     return hipGetLastError();
 }
 
 template <typename R, int GK, int L, int T, bool COMP>
 hipError_t occ_one(int *blocks)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, pdhg_step_kernel<R, OMT_K, GK, L, T, COMP>,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, pdhg_step_kernel<R, OMT_K, GK, L, T, COMP, false>,
                                                          WAVE * STEP_WAVES_PER_WG, 0);
 }
 

@@ -213,6 +213,125 @@ constexpr int edge_b(int e)
     return a + 1 + (e - complete_row_start(K, a));
 }
 
+// ------------------------------------------------------------ check terms
+//
+// For one step (u, w, phi) -> (u', w', phi') every pixel contributes, in
+// FP64, the terms listed in metrics_device.h.
+
+// div_G of w' - w (dgd) and of w' (dg1) at channel c, in edge order:
+// D diag(1/c) applied to the transfer (div_G is its negative).
+template <typename R, int K, int GK, int LA, typename W>
+__device__ __forceinline__ void graph_div_terms(const StepArgs<R> &a, int c, const W (&we0)[LA], const W (&we1)[LA],
+                                                double &dgd, double &dg1)
+{
+    dgd = 0.0;
+    dg1 = 0.0;
+#pragma unroll
+    for (int e = 0; e < LA; ++e) {
+        if constexpr (GK == G_DENSE || is_matrix_kind(GK)) {
+            dgd += double(a.gm[c * LMAX + e]) * (double(we1[e]) - double(we0[e]));
+            dg1 += double(a.gm[c * LMAX + e]) * double(we1[e]);
+        } else {
+            if (edge_a<GK, K>(e) == c) {
+                dgd += double(a.ic[e]) * (double(we1[e]) - double(we0[e]));
+                dg1 += double(a.ic[e]) * double(we1[e]);
+            }
+            if (edge_b<GK, K>(e) == c) {
+                dgd -= double(a.ic[e]) * (double(we1[e]) - double(we0[e]));
+                dg1 -= double(a.ic[e]) * double(we1[e]);
+            }
+        }
+    }
+}
+
+// The check terms of one channel of one pixel, added to the pixel's sums
+// acc in a fixed order.  Arguments are the old (0) and new (1) values:
+// potential p, flux (ux, uy) at the pixel, u_x of the pixel above (xl) and
+// u_y of the pixel to the left (yl), each already zero where App. A's ghost
+// rules make it so; dgd, dg1 from graph_div_terms; fc the source.  sq and
+// u2 collect squares for the regulariser and the ||u||_2 norm.  Every path
+// that takes a check (the separate metrics pass and the check fused into
+// the step) calls this, then pixel_terms, then adds the pixel's sums to its
+// column's, so both give the same bits.
+__device__ __forceinline__ void chan_terms(double (&acc)[NMET], double &sq, double &u2, int unorm, double inv_h,
+                                           double p0, double p1, double ux0, double ux1, double uy0, double uy1,
+                                           double xl0, double xl1, double yl0, double yl1, double dgd, double dg1,
+                                           double fc)
+{
+    const double dp = p1 - p0;
+    const double dux = ux1 - ux0, duy = uy1 - uy0;
+    const double ddiv = ((dux - (xl1 - xl0)) + duy - (yl1 - yl0)) * inv_h;
+    const double div1 = ((ux1 - xl1) + uy1 - yl1) * inv_h;
+    acc[0] += dux * dux + duy * duy;
+    acc[2] += dp * dp;
+    acc[3] += dp * (ddiv - dgd);
+    acc[5] += p1 * fc;
+    const double r = (div1 - dg1) + fc;
+    acc[6] += r * r;
+    acc[7] += p1;
+    sq += ux1 * ux1 + uy1 * uy1;
+    if (unorm == 0)
+        acc[4] += sqrt(ux1 * ux1 + uy1 * uy1);
+    else if (unorm == 1)
+        acc[4] += fabs(ux1) + fabs(uy1);
+    else
+        u2 += ux1 * ux1 + uy1 * uy1;
+}
+
+// The transfer and norm terms of one pixel of the vector method, after its
+// channels: ||u||_2 (u norm 2), |w' - w|^2, alpha ||w'||_w and the
+// regulariser.  Transfers past the l in use (a dense graph's bucket) are 0.
+template <int LA, typename W>
+__device__ __forceinline__ void pixel_terms(double (&acc)[NMET], double sq, double u2, int unorm, int wnorm,
+                                            double alpha, double eps, int l, const W (&we0)[LA], const W (&we1)[LA])
+{
+    if (unorm == 2) acc[4] += sqrt(u2);
+    double wn = 0.0, w2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < LA; ++e) {
+        const double x0 = e < l ? double(we0[e]) : 0.0, x1 = e < l ? double(we1[e]) : 0.0;
+        acc[1] += (x1 - x0) * (x1 - x0);
+        wn += fabs(x1);
+        w2 += x1 * x1;
+    }
+    acc[4] += alpha * (wnorm == 0 ? wn : sqrt(w2));
+    if (eps > 0.0) acc[4] += eps * (sq + w2);  // quadratic regularisation
+}
+
+// Sum over the 64 lanes of a wave; lane 0 holds the result.  The tree adds
+// neighbouring lanes first (offsets 1, 2, 4, ..., 32), so lane 4q holds the
+// sum of its quad of columns after the first two levels: a check fused into
+// a strip of any width (a whole number of 4-column quads) reproduces those
+// quad sums, and quads_to_tiles the remaining levels.
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) x += __shfl_down(x, off, WAVE);
+    return x;
+}
+
+// ------------------------------------------------------------ fused check
+//
+// A check launch (CHK) takes the check of Sec. 6.1 in the same pass as the
+// iteration: the last stage, which holds both the old and the new iterate of
+// every pixel it stores, adds the pixel's check terms (chan_terms and
+// pixel_terms above, the same code as the separate metrics pass) to
+// per-column sums over an aligned block of MET_ROWS rows, and at
+// the end of each block adds the columns of every aligned 4-column quad as
+// the first two levels of wave_sum do.  Every launch shape stores whole
+// quads (strips are 64 - 2T columns wide from column (64 - 2T) wc, and
+// 64 - 2T is a multiple of 4 for T = 1, 2, 4, 8), so the quad sums, and the
+// tiles and totals formed from them in a fixed order, do not depend on the
+// launch shape and equal those of the separate pass bit for bit.  (The host
+// takes checks in single-iteration launches only: with the check, a
+// two-iteration launch at k = 8 needs more than 256 registers.)
+template <typename R, int K>
+struct ChkState {
+    R xo[K], xn[K];       // old and new u_x of this lane's pixel on the row above
+    double col[NMET];     // this column's sums over the current row block
+    int qlane;            // lane % 4 of the first column of each quad
+};
+
 // ------------------------------------------------------------ one stage
 
 // Columns just outside an aligned strip, lane c holding channel c: the
@@ -234,13 +353,18 @@ struct Edges {
 // the aligned mode (ALN) lane 63 takes its right potential and lane 0 its
 // left flux from E instead of the neighbouring lane; the left flux is
 // recomputed with the same expressions as every other pixel's.
-template <typename R, int K, int GK, int L, int LA, bool COMP, bool ALN>
+//
+// CHK (a check launch's last stage): also add this row's check terms to ck
+// (pixel row r, column j, counted where it is stored) and, at the end of an
+// aligned block of MET_ROWS rows, store the block's quad sums to a.qpart.
+template <typename R, int K, int GK, int L, int LA, bool COMP, bool ALN, bool CHK = false>
 __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_ok, bool last_row, bool last_col,
                                       const R (&pA)[K], const R (&pAl)[K], const R (&pB)[K], const R (&pBl)[K],
                                       const R (&ux)[K], const R (&uy)[K], const R (&w)[LA], const R (&f)[K],
                                       const Edges<R> &E, bool st_row, int64_t ro, unsigned soff, int64_t P,
                                       R (&carry)[K], R (&pO)[K],
-                                      R (&pOl)[K], R (&uxO)[K], R (&uyO)[K], R (&wO)[LA])
+                                      R (&pOl)[K], R (&uxO)[K], R (&uyO)[K], R (&wO)[LA],
+                                      ChkState<R, K> &ck, int r = 0, int j = 0)
 {
     // this row of every output field (zero-length descriptors unless st_row)
     const unsigned Psz = unsigned(P) * unsigned(sizeof(R)), Pszl = unsigned(P) * 4u;
@@ -301,6 +425,10 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
             if (L > 0) buf_st<R>(rw, soff + unsigned(e) * Psz, wt[e]);
         }
     }
+
+    double cacc[NMET], csq = 0.0, cu2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NMET; ++q) cacc[q] = 0.0;
 
     // u~ = u + mu grad_x phi for this lane's pixel and, in the aligned mode,
     // for the pixel left of the strip (wave-uniform)
@@ -431,6 +559,7 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         const R ubx = R(2) * bx - ux[c];
         const R uby = R(2) * by - uy[c];
         R ubl = lane_prev(uby);
+        R ynl = CHK ? lane_prev(by) : R(0), yol = CHK ? lane_prev(uy[c]) : R(0);  // u_y left: new, old
         if (ALN) {
             R ex, ey, ebx, eby;
             utilde_left(c, ex, ey);
@@ -446,6 +575,10 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
             eby = eby * a.ureg;
             const R el = E.hasL ? R(2) * eby - lane_get(E.Luy, c) : R(0);
             if (lane == 0) ubl = el;
+            if (CHK && lane == 0) {
+                ynl = E.hasL ? eby : R(0);
+                yol = E.hasL ? lane_get(E.Luy, c) : R(0);
+            }
         }
         const R dx = (((ubx - carry[c]) + uby) - ubl) * a.inv_h;
         // div_G(w) = -D diag(1/c) w: dg is D diag(1/c) w, accumulated in edge order
@@ -483,6 +616,44 @@ __device__ __forceinline__ void stage(const StepArgs<R> &a, int lane, bool lane_
         if (COMP) buf_st<float>(rplo, soffl + unsigned(c) * Pszl, float(pol));
         buf_st<R>(ru, soff + unsigned(c) * Psz, bx);
         buf_st<R>(ru, soff + unsigned(K + c) * Psz, by);
+        if constexpr (CHK) {
+            // the values the separate metrics pass reads back, ghosts zeroed
+            const double p0 = COMP ? double(pA[c]) + double(pAl[c]) : double(pA[c]);
+            const double p1 = COMP ? double(po) + double(pol) : double(po);
+            const bool gx = r < a.m - 1, gy = j < a.n - 1;
+            const double ux0 = gx ? double(ux[c]) : 0.0, ux1 = gx ? double(bx) : 0.0;
+            const double uy0 = gy ? double(uy[c]) : 0.0, uy1 = gy ? double(by) : 0.0;
+            const double xl0 = r > 0 ? double(ck.xo[c]) : 0.0, xl1 = r > 0 ? double(ck.xn[c]) : 0.0;
+            const double yl0 = j > 0 ? double(yol) : 0.0, yl1 = j > 0 ? double(ynl) : 0.0;
+            double dgd = 0.0, dg1 = 0.0;
+            if constexpr (L > 0) graph_div_terms<R, K, GK, LA>(a, c, w, wO, dgd, dg1);
+            chan_terms(cacc, csq, cu2, unorm, double(a.inv_h), p0, p1, ux0, ux1, uy0, uy1, xl0, xl1, yl0, yl1, dgd,
+                       dg1, double(f[c]));
+            ck.xo[c] = ux[c];
+            ck.xn[c] = bx;
+        }
+    }
+    if constexpr (CHK) {
+        pixel_terms<LA>(cacc, csq, cu2, unorm, wnorm, a.alpha, a.eps, L > 0 ? a.l : 0, w, wO);
+        // a pixel this launch stores is counted, once
+        const bool mine = st_row && soff != OFF_NONE;
+#pragma unroll
+        for (int q = 0; q < NMET; ++q) ck.col[q] += mine ? cacc[q] : 0.0;
+        // end of an aligned row block (wave-uniform): quad sums of the columns
+        if (st_row && (r % MET_ROWS == MET_ROWS - 1 || r == a.m - 1)) {
+            // a quad's first column sits on lanes with lane % 4 == ck.qlane;
+            // it stores if its column is one this strip stores
+            const bool base = (lane & 3) == ck.qlane && soff != OFF_NONE;
+            double *dst = a.qpart + (int64_t)(r / MET_ROWS) * a.nq + (j >> 2);
+#pragma unroll
+            for (int q = 0; q < NMET; ++q) {
+                double x = ck.col[q];
+                x += __shfl_down(x, 1u, WAVE);
+                x += __shfl_down(x, 2u, WAVE);
+                if (base) dst[q * a.qstride] = x;
+                ck.col[q] = 0.0;
+            }
+        }
     }
 }
 
@@ -498,7 +669,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nwg)
 }
 
 // T iterations on the strip (column block wc, row chunk wr) of one wave.
-template <typename R, int K, int GK, int L, int T, bool COMP>
+// CHK: a check launch (rows per wave a multiple of MET_ROWS; a.qpart set).
+template <typename R, int K, int GK, int L, int T, bool COMP, bool CHK = false>
 __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int wr, int lane)
 {
     constexpr int LA = L > 0 ? L : 1;
@@ -617,6 +789,13 @@ __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int 
         for (int e = 0; e < LA; ++e) wP[t][e] = wN[t][e] = R(0);
     }
 
+    ChkState<R, K> ck;
+#pragma unroll
+    for (int c = 0; c < K; ++c) ck.xo[c] = ck.xn[c] = R(0);
+#pragma unroll
+    for (int q = 0; q < NMET; ++q) ck.col[q] = 0.0;
+    ck.qlane = ALN ? 0 : (T & 3);  // the strip's first stored column is on lane T (lane 0 aligned)
+
     const int nsteps = (re - rs) + T - 1;
     for (int s = 0; s < nsteps; ++s) {
         const int r0 = rs + s;
@@ -675,17 +854,25 @@ __device__ __forceinline__ void process_strip(const StepArgs<R> &a, int wc, int 
                 const bool last_row = (r == a.m - 1);
                 const bool st_row = (t == T - 1) && r >= i0 && r < i1;
                 const int64_t ro = (int64_t)r * pitch;
+                // the last stage of a check launch also takes the check
+                constexpr bool CK0 = CHK && T == 1;
                 if (t == 0) {
                     Edges<R> E{cRA, cRAl, cLA, cLAl, cLB, cLBl, cLux, cLuy, hasL};
-                    stage<R, K, GK, L, LA, COMP, ALN>(a, lane, jin, last_row, last_col, cA, cAl, cB, cBl, cux, cuy,
-                                                      cw, fq[0], E, st_row, ro, soff, P, carry[0], phN[0], plN[0], uxN[0], uyN[0],
-                                                      wN[0]);
+                    stage<R, K, GK, L, LA, COMP, ALN, CK0>(a, lane, jin, last_row, last_col, cA, cAl, cB, cBl, cux,
+                                                           cuy, cw, fq[0], E, st_row, ro, soff, P, carry[0], phN[0],
+                                                           plN[0], uxN[0], uyN[0], wN[0], ck, r, j);
+                } else if (CHK && t == T - 1) {
+                    Edges<R> E{R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), false};
+                    stage<R, K, GK, L, LA, COMP, false, CHK>(a, lane, jin, last_row, last_col, phP[t - 1],
+                                                             plP[t - 1], phN[t - 1], plN[t - 1], uxP[t - 1], uyP[t - 1],
+                                                             wP[t - 1], fq[t], E, st_row, ro, soff, P, carry[t], phN[t],
+                                                             plN[t], uxN[t], uyN[t], wN[t], ck, r, j);
                 } else {
                     Edges<R> E{R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), false};
                     stage<R, K, GK, L, LA, COMP, false>(a, lane, jin, last_row, last_col, phP[t - 1], plP[t - 1],
                                                         phN[t - 1], plN[t - 1], uxP[t - 1], uyP[t - 1], wP[t - 1],
                                                         fq[t], E, st_row, ro, soff, P, carry[t], phN[t], plN[t], uxN[t], uyN[t],
-                                                        wN[t]);
+                                                        wN[t], ck, r, j);
                 }
             }
         }

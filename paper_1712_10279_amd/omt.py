@@ -83,6 +83,7 @@ _SIGS = {
     "omt_batch_distance": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "omt_batch_grad": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "omt_batch_get_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "omt_batch_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "omt_batch_destroy": (C.c_int, [C.c_void_p]),
     "omt_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]),
@@ -468,6 +469,11 @@ class BatchSolver:
         _check(lib().omt_batch_get_state(self._h, int(b), _ptr(phi), _ptr(u), _ptr(w) if l else C.c_void_p(0)),
                "omt_batch_get_state")
         return {"phi": phi, "u": u, "w": w[:, :, :l]}
+
+    def set_state(self, b, phi=None, u=None, w=None):
+        """Warm start of problem b (see Solver.set_state)."""
+        keep = [t.contiguous() if t is not None else None for t in (phi, u, w)]
+        _check(lib().omt_batch_set_state(self._h, int(b), *[_ptr(t) for t in keep]), "omt_batch_set_state")
 
 
 # ----------------------------------------------------------------- matrix OMT
