@@ -9,7 +9,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "omt_oracle.c"), os.path.join(HERE, "momt_oracle.c")]
+SRCS = [os.path.join(HERE, "omt_oracle.c"), os.path.join(HERE, "momt_oracle.c"), os.path.join(HERE, "omt3_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -257,3 +257,66 @@ def warm_state(seed: int, m: int, n: int, k: int, l: int, u_scale: float, w_scal
     u = rng.uniform(-u_scale, u_scale, size=(m, n, k, 2))
     w = rng.uniform(-w_scale, w_scale, size=(m, n, l))
     return phi, u, w
+
+
+# ------------------------------------------------------------- 3-D grids
+#
+# The same generator on an m x n x p grid (centres uniform over the volume,
+# isotropic 3-D Gaussian bumps): there are no 3-D images in the paper, whose
+# Sec. 8.2 names 3-D imaging as future work.
+
+def gaussian_mixture3(m: int, n: int, p: int, k: int, bumps: int, sig_lo: float, sig_hi: float, floor: float,
+                      rng: np.random.Generator, channel_mass=None) -> np.ndarray:
+    """(m, n, p, k) float64 cell masses, unit total mass (or the given
+    split over the channels)."""
+    ii = np.arange(m, dtype=np.float64)
+    jj = np.arange(n, dtype=np.float64)
+    zz = np.arange(p, dtype=np.float64)
+    out = np.zeros((m, n, p, k), dtype=np.float64)
+    for c in range(k):
+        acc = np.full((m, n, p), floor, dtype=np.float64)
+        for _ in range(bumps):
+            x0, y0, z0 = rng.uniform(0.0, m), rng.uniform(0.0, n), rng.uniform(0.0, p)
+            sig = rng.uniform(sig_lo, sig_hi)
+            amp = rng.uniform(0.5, 1.5)
+            gi = np.exp(-((ii - x0) ** 2) / (2.0 * sig * sig))
+            gj = np.exp(-((jj - y0) ** 2) / (2.0 * sig * sig))
+            gz = np.exp(-((zz - z0) ** 2) / (2.0 * sig * sig))
+            acc += amp * gi[:, None, None] * gj[None, :, None] * gz[None, None, :]
+        out[..., c] = acc
+    if channel_mass is None:
+        out /= out.sum()
+    else:
+        cm = np.asarray(channel_mass, dtype=np.float64)
+        cm = cm / cm.sum()
+        for c in range(k):
+            out[..., c] *= cm[c] / out[..., c].sum()
+    return out
+
+
+def pair3(cfg: int, pair_id: int, m: int, n: int, p: int, k: int, bumps: int, sig_lo: float, sig_hi: float,
+          floor: float, channel_mass0=None, channel_mass1=None):
+    """(rho0, rho1) of a 3-D workload pair, seeded like ``pair``."""
+    r0 = np.random.default_rng(np.random.SeedSequence([cfg, pair_id, 0, p]))
+    r1 = np.random.default_rng(np.random.SeedSequence([cfg, pair_id, 1, p]))
+    rho0 = gaussian_mixture3(m, n, p, k, bumps, sig_lo, sig_hi, floor, r0, channel_mass0)
+    rho1 = gaussian_mixture3(m, n, p, k, bumps, sig_lo, sig_hi, floor, r1, channel_mass1)
+    return rho0, rho1
+
+
+def random_volume_pair(seed: int, m: int, n: int, p: int, k: int, bumps: int = 3, floor: float = 1e-3):
+    """Small generic 3-D pair for tests (cfg id 101)."""
+    lo = max(1.0, min(m, n, p) / 12.0)
+    hi = max(2.0, min(m, n, p) / 4.0)
+    return pair3(101, seed, m, n, p, k, bumps, lo, hi, floor)
+
+
+def volume_256(m: int = 256, n: int = 256, p: int = 128, k: int = 3):
+    """3-D workload: 256 x 256 x 128 cells, k = 3 triangle, alpha 1, 16 bumps
+    per channel with sigma in [8, 32] cells, floor 1e-3, unit mass; the
+    8.4-million-cell volume is the size of the 2-D large workload's
+    1024 x 1024 x 8 pixel-channels."""
+    s = min(m, n, p) / 128.0
+    rho0, rho1 = pair3(6, 0, m, n, p, k, 16, max(8.0 * s, 1.0), max(32.0 * s, 2.0), 1e-3)
+    return dict(name=f"vomt3_{m}x{n}x{p}_k{k}_triangle", rho0=rho0, rho1=rho1, edges=TRIANGLE, alpha=1.0,
+                tau=default_tau(max(m, n), max(n, p)), iters=2000, dtype="f32")

@@ -190,3 +190,41 @@ def w1_triangle(a, b):
 def w1_path(a, b):
     """W1 on the unit-cost path graph: sum of |cumulative differences|."""
     return np.abs(np.cumsum(a - b, axis=-1)[..., :-1]).sum(axis=-1)
+
+
+def lp_value3(rho0, rho1, edges, cost, alpha, h):
+    """Exact V for the norms ||u||_1, ||w||_1 on an m x n x p grid: min-cost
+    flow on (3-D grid) x G, arcs of cost h between face neighbours along each
+    axis and alpha c_e between the channels of an edge at one pixel."""
+    from scipy.optimize import linprog
+    from scipy.sparse import coo_matrix
+
+    m, n, p, k = rho0.shape
+    node = lambda i, j, z, c: ((i * n + j) * p + z) * k + c  # noqa: E731
+    rows, cols, vals, costs = [], [], [], []
+    a = 0
+
+    def arc(s, t, cst):
+        nonlocal a
+        rows.extend([s, t])
+        cols.extend([a, a])
+        vals.extend([1.0, -1.0])
+        costs.append(cst)
+        a += 1
+
+    for i in range(m):
+        for j in range(n):
+            for z in range(p):
+                for c in range(k):
+                    for (di, dj, dz) in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+                        if i + di < m and j + dj < n and z + dz < p:
+                            arc(node(i, j, z, c), node(i + di, j + dj, z + dz, c), h)
+                            arc(node(i + di, j + dj, z + dz, c), node(i, j, z, c), h)
+                for e, (q0, q1) in enumerate(edges):
+                    arc(node(i, j, z, q0), node(i, j, z, q1), alpha * cost[e])
+                    arc(node(i, j, z, q1), node(i, j, z, q0), alpha * cost[e])
+    A = coo_matrix((vals, (rows, cols)), shape=(m * n * p * k, a)).tocsr()
+    b = (rho0 - rho1).reshape(-1)
+    res = linprog(np.array(costs), A_eq=A, b_eq=b, bounds=(0, None), method="highs")
+    assert res.status == 0, res.message
+    return float(res.fun)

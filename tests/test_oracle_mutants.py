@@ -92,3 +92,38 @@ def test_matrix_pins_reject_mutant(tmp_path, name, old, new):
                         os.path.join(ROOT, "tests", "test_moracle_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant '{name}' survived the pins:\n{r.stdout[-2000:]}"
+
+
+SRC3 = os.path.join(ROOT, "oracle", "omt3_oracle.c")
+
+GRID3_MUTANTS = [
+    ("u_z left out of the flux block", "double v[3] = {bx[c], by[c], bz[c]};", "double v[3] = {bx[c], by[c], 0.0};"),
+    ("wrong z neighbour in div_x", "zl = z > 0 ? uz[ID4(i, j, z - 1, c, n, p, k)] : 0.0;",
+     "zl = z > 1 ? uz[ID4(i, j, z - 2, c, n, p, k)] : 0.0;"),
+    ("z gradient towards z - 1", "gz[o] = z < p - 1 ? (phi[ID4(i, j, z + 1, c, n, p, k)] - phi[o]) / h : 0.0;",
+     "gz[o] = (z < p - 1 && z > 0) ? (phi[o] - phi[ID4(i, j, z - 1, c, n, p, k)]) / h : 0.0;"),
+    ("u_z extrapolation dropped", "bz[s] = 2.0 * uz1[s] - uz[s];", "bz[s] = uz1[s];"),
+    ("2-D step rule on the 3-D grid", "if (q->mu <= 0.0) q->mu = q->h * q->h / (48.0 * q->tau);",
+     "if (q->mu <= 0.0) q->mu = q->h * q->h / (32.0 * q->tau);"),
+    ("u_z left out of the objective", "s += sqrt(bx[c] * bx[c] + by[c] * by[c] + bz[c] * bz[c]);",
+     "s += sqrt(bx[c] * bx[c] + by[c] * by[c]);"),
+    ("y and z swapped in the gradient", "gy[o] = j < n - 1 ? (phi[ID4(i, j + 1, z, c, n, p, k)] - phi[o]) / h : 0.0;",
+     "gy[o] = (j < n - 1 && z < p - 1) ? (phi[ID4(i, j, z + 1, c, n, p, k)] - phi[o]) / h : 0.0;"),
+]
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+@pytest.mark.parametrize("name,old,new", GRID3_MUTANTS, ids=[m[0] for m in GRID3_MUTANTS])
+def test_grid3_pins_reject_mutant(tmp_path, name, old, new):
+    src = open(SRC3).read()
+    assert old in src, f"pattern for '{name}' not found"
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new, 1))
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-o", str(so), SRC, str(mut),
+                    "-lm"], check=True)
+    env = dict(os.environ, OMT_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle3_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant '{name}' survived the pins:\n{r.stdout[-2000:]}"
