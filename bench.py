@@ -42,10 +42,11 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations for the CPU baseline (0: auto)")
     ap.add_argument("--timing-launches", type=int, default=200)
-    ap.add_argument("--workload", default="large", choices=["large", "batched", "rgb", "loss", "matrix"],
+    ap.add_argument("--workload", default="large", choices=["large", "batched", "rgb", "loss", "matrix", "volume"],
                     help="large: 1024x1024 k=8 throughput (default); batched: 96 pairs to 1e-5, batched vs "
                          "plain; rgb: 256x256 k=3 time to 1e-5; loss: 8 pairs of 512x512 forward+backward; "
-                         "matrix: 3x3 matrix OMT, 256x256 time to a 1e-3 gap and 1024x1024 step roofline")
+                         "matrix: 3x3 matrix OMT, 256x256 time to a 1e-3 gap and 1024x1024 step roofline; "
+                         "volume: 3-D grid 256x256x128, k=3 throughput")
     ap.add_argument("--pairs", type=int, default=96, help="batched workload: number of pairs")
     ap.add_argument("--tol", type=float, default=0.0, help="time-to-tolerance workloads: tolerance (0: workload's)")
     ap.add_argument("--cap", type=int, default=3_000_000, help="time-to-tolerance workloads: iteration cap")
@@ -311,6 +312,70 @@ def bench_matrix(a):
                  cell_iter_per_s=1024 * 1024 * T / (us * 1e-6))
 
 
+def bench_volume(a):
+    """3-D grid (256 x 256 x 128 cells, k = 3 triangle, alpha 1, FP32): one
+    step is a whole solve of 2,000 iterations with checks every 64; the step
+    kernel against the HBM roofline."""
+    import torch
+    from paper_1712_10279_amd import inputs as I
+    from paper_1712_10279_amd import omt
+    d = I.volume_256()
+    m, n, p, k = d["rho0"].shape
+    l = len(d["edges"])
+    iters = a.iters or d["iters"]
+    r0 = torch.as_tensor(d["rho0"], dtype=torch.float32, device="cuda")
+    r1 = torch.as_tensor(d["rho1"], dtype=torch.float32, device="cuda")
+    rows = a.rows
+    if rows == 0:
+        s = omt.Solver(r0, r1, d["edges"], alpha=d["alpha"], tau=d["tau"])
+        _, rows, _ = s.autotune()
+        del s
+
+    def one_solve():
+        s = omt.Solver(r0, r1, d["edges"], alpha=d["alpha"], tau=d["tau"], rows_per_wave=rows)
+        info = s.solve(iters, 0.0, 64)
+        V, _ = s.distance()
+        s.grad()
+        return s, info, V
+
+    for _ in range(a.warmup):
+        one_solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        s, info, V = one_solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cells = m * n * p
+    value = cells * iters * a.steps / dt
+    st = s.get_state()
+    u_act = float(((st["u"] != 0).reshape(cells, -1).any(dim=1)).double().mean())
+    w_act = float(((st["w"] != 0).reshape(cells, -1).any(dim=1)).double().mean())
+    us = s.time_steps(1, rows, max(1, a.timing_launches))
+    alg = (9 * k + 2 * l) * 4 * cells  # reads phi k, u 3k, w l, f k; writes phi k, u 3k, w l
+    ach = alg / (us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": None, "kernel": "pdhg_step3_kernel (one iteration per launch)", "us_per_launch": us,
+            "bytes_per_launch": alg}
+    line = _line("PDHG cell-iterations/s, 3-D grid", value, "cell-iter/s", a.steps, a.warmup, dt * 1e3 / a.steps,
+                 config={"workload": d["name"], "grid": [m, n, p], "channels": k, "edges": l, "graph": "triangle",
+                         "alpha": d["alpha"], "tau": d["tau"], "iterations_per_step": iters, "check_every": 64,
+                         "slices_per_wave": rows, "parallelism": "single-gpu"},
+                 roofline=roof, solve={"primal": V, "residual": info["residual"], "rel_gap": info["rel_gap"],
+                                       "u_active": u_act, "w_active": w_act})
+    if not a.no_cpu:
+        import oracle.grid3 as G3
+        q = G3.Problem3(m, n, p, k, edges=d["edges"], alpha=d["alpha"], tau=d["tau"])
+        f, _ = G3.prepare_f(d["rho0"].astype("float32").astype("float64"),
+                            d["rho1"].astype("float32").astype("float64"), q.edges)
+        ci = a.cpu_iters or 8
+        r = G3.solve(q, f, ci, 0.0, 1 << 30)
+        line["cpu_baseline"] = {"value": cells * ci / r["wall_s"], "unit": "cell-iter/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{ci} FP64 iterations of the same {m}x{n}x{p}x{k} grid, single thread, "
+                                          f"{r['wall_s']:.1f} s"}
+    return line
+
+
 def main():
     a = _parse()
     if a.copy_calibration:
@@ -320,7 +385,8 @@ def main():
         if a.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus})", file=sys.stderr)
             sys.exit(2)
-        fn = {"batched": bench_batched, "rgb": bench_rgb, "loss": bench_loss, "matrix": bench_matrix}[a.workload]
+        fn = {"batched": bench_batched, "rgb": bench_rgb, "loss": bench_loss, "matrix": bench_matrix,
+              "volume": bench_volume}[a.workload]
         print(json.dumps(fn(a)), flush=True)
         return
     if a.gpus != 1:

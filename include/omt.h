@@ -103,6 +103,18 @@ typedef struct {
     double reg_eps;            /* >= 0: quadratic regularisation eps (|u|^2 + |w|^2), Euclidean squares of
                                   all components (Sec. 9); each shrink is then divided by 1 + 2 t eps with
                                   t = mu for u and nu for w.  0 gives the method of Sec. 7.2 exactly. */
+    int32_t p;                 /* depth of a 3-D grid (slices along the third axis z); 0 or 1: the 2-D
+                                  grid.  The paper states the method in 2-D and names 3-D as future work
+                                  (Sec. 8.2); with p > 1 App. A's discretisation is applied along z too:
+                                  u gains a third component per channel (u_z, zero on the last slice),
+                                  h = 1/(max(m,n,p)-1), and the mu rule becomes h^2/(48 tau) (h^2/(24 tau)
+                                  without edges), since the 3-D Laplacian's spectrum reaches 12/h^2 where
+                                  the 2-D one reaches 8/h^2.  Densities are then m x n x p x k (channel
+                                  fastest, z next), u m x n x p x k x 3, w m x n x p x l.  Compiled for
+                                  k = 1 (no edges), k = 2 (one edge) and k = 3 (up to three edges), FP32 or
+                                  FP64, one iteration per launch, without the compensated potential;
+                                  OMT_EUNSUPPORTED otherwise.  rows_per_wave then counts the slices a
+                                  wavefront marches through (0: chosen to fill the chip). */
 } omt_params;
 
 typedef struct {

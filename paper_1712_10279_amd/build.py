@@ -37,6 +37,7 @@ def _units():
     units = []
     for k in range(1, KMAX + 1):
         units.append((os.path.join(CSRC, "step.hip"), os.path.join(OBJ, f"step_k{k}.o"), [f"-DOMT_K={k}"]))
+    units.append((os.path.join(CSRC, "step3.hip"), os.path.join(OBJ, "step3.o"), []))
     units.append((os.path.join(CSRC, "aux.hip"), os.path.join(OBJ, "aux.o"), []))
     units.append((os.path.join(CSRC, "batch.hip"), os.path.join(OBJ, "batch.o"), []))
     units.append((os.path.join(CSRC, "omt_api.cpp"), os.path.join(OBJ, "omt_api.o"), ["-x", "hip"]))

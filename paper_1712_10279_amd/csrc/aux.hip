@@ -98,15 +98,27 @@ __global__ __launch_bounds__(RB) void sums_kernel(SumsArgs a)
     if (threadIdx.x == 0) a.partials[(int64_t)blockIdx.x * W + 4 * a.k] = o1[0];
 }
 
+// Pixel pp of the caller's layout (i, j and, on a 3-D grid, z; channel
+// fastest) -> its offset within a plane: row z m + i, column j.
+__device__ __forceinline__ int64_t plane_offset(int64_t pp, int m, int n, int p3, int pitch, int &i, int &j, int &z)
+{
+    z = int(pp % p3);
+    const int64_t t = pp / p3;
+    j = int(t % n);
+    i = int(t / n);
+    return ((int64_t)z * m + i) * pitch + j;
+}
+
 __global__ void make_f_kernel(MakeFArgs a)
 {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= (int64_t)a.m * a.n) return;
-    const int i = int(p / a.n), j = int(p % a.n);
+    if (p >= (int64_t)a.m * a.n * a.p) return;
+    int i, j, z;
+    const int64_t o = plane_offset(p, a.m, a.n, a.p, a.pitch, i, j, z);
     for (int c = 0; c < a.k; ++c) {
         const double x0 = ldv(a.rho0, a.dtype, p * a.k + c);
         const double x1 = ldv(a.rho1, a.dtype, p * a.k + c);
-        stv(a.f, a.dtype, c * a.plane + (int64_t)i * a.pitch + j, (x1 - x0) - a.shift[c]);
+        stv(a.f, a.dtype, c * a.plane + o, (x1 - x0) - a.shift[c]);
     }
 }
 
@@ -170,10 +182,11 @@ __global__ __launch_bounds__(RB) void plane_sums_kernel(PlaneSumArgs a)
 __global__ void xfer_kernel(XferArgs a)
 {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= (int64_t)a.m * a.n) return;
-    const int i = int(p / a.n), j = int(p % a.n);
-    const int64_t o = (int64_t)i * a.pitch + j;
+    if (p >= (int64_t)a.m * a.n * a.p) return;
+    int i, j, z;
+    const int64_t o = plane_offset(p, a.m, a.n, a.p, a.pitch, i, j, z);
     const int k = a.k;
+    const int nc = a.p > 1 ? 3 : 2;  // flux components per channel
     switch (a.mode) {
         case 0:  // exported potential: sign * (-(phi - mean))
             for (int c = 0; c < k; ++c) {
@@ -182,11 +195,10 @@ __global__ void xfer_kernel(XferArgs a)
                 stv(a.dst, a.dtype, p * k + c, a.sign * (-(x - a.mean[c])));
             }
             break;
-        case 1:  // u planes -> m x n x k x 2
-            for (int c = 0; c < k; ++c) {
-                stv(a.dst, a.dtype, (p * k + c) * 2 + 0, ldv(a.src, a.dtype, c * a.plane + o));
-                stv(a.dst, a.dtype, (p * k + c) * 2 + 1, ldv(a.src, a.dtype, (k + c) * a.plane + o));
-            }
+        case 1:  // u planes -> m x n (x p) x k x nc
+            for (int c = 0; c < k; ++c)
+                for (int d = 0; d < nc; ++d)
+                    stv(a.dst, a.dtype, (p * k + c) * nc + d, ldv(a.src, a.dtype, (d * k + c) * a.plane + o));
             break;
         case 2:  // planes -> m x n x k (w, or phi when plo is null)
             for (int c = 0; c < k; ++c) {
@@ -201,12 +213,16 @@ __global__ void xfer_kernel(XferArgs a)
                 if (a.plo_out) a.plo_out[c * a.plane + o] = 0.0f;
             }
             break;
-        case 4:  // m x n x k x 2 -> u planes, ghosts zeroed (App. A)
+        case 4:  // m x n (x p) x k x nc -> u planes, ghosts zeroed (App. A)
             for (int c = 0; c < k; ++c) {
-                const double x = (a.src && i < a.m - 1) ? ldv(a.src, a.dtype, (p * k + c) * 2 + 0) : 0.0;
-                const double y = (a.src && j < a.n - 1) ? ldv(a.src, a.dtype, (p * k + c) * 2 + 1) : 0.0;
+                const double x = (a.src && i < a.m - 1) ? ldv(a.src, a.dtype, (p * k + c) * nc + 0) : 0.0;
+                const double y = (a.src && j < a.n - 1) ? ldv(a.src, a.dtype, (p * k + c) * nc + 1) : 0.0;
                 stv(a.dst, a.dtype, c * a.plane + o, x);
                 stv(a.dst, a.dtype, (k + c) * a.plane + o, y);
+                if (nc == 3) {
+                    const double zz = (a.src && z < a.p - 1) ? ldv(a.src, a.dtype, (p * k + c) * nc + 2) : 0.0;
+                    stv(a.dst, a.dtype, (2 * k + c) * a.plane + o, zz);
+                }
             }
             break;
         default:
@@ -286,7 +302,7 @@ hipError_t launch_sums(const SumsArgs &a, hipStream_t s)
 
 hipError_t launch_make_f(const MakeFArgs &a, hipStream_t s)
 {
-    const int64_t n = (int64_t)a.m * a.n;
+    const int64_t n = (int64_t)a.m * a.n * a.p;
     hipLaunchKernelGGL(make_f_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -319,7 +335,8 @@ hipError_t launch_plane_sums(const PlaneSumArgs &a, hipStream_t s)
 
 hipError_t launch_xfer(const XferArgs &a, hipStream_t s)
 {
-    const int64_t n = (int64_t)a.m * a.n;
+    if (a.p < 1) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)a.m * a.n * a.p;
     hipLaunchKernelGGL(xfer_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -21,6 +21,7 @@
 
 #include "../../include/omt.h"
 #include "../../include/omt_matrix.h"
+#include "grid3.h"
 #include "omt_kernels.h"
 
 #include <complex>
@@ -196,6 +197,7 @@ void jacobi_eigenvalues(double *A, int k, double *ev)
 
 struct Resolved {
     int m, n, k, l, gk, lb;
+    int p = 1;  // slices of a 3-D grid (1: the 2-D grid)
     // fixed-size members: resolving a vector problem allocates nothing
     std::array<int32_t, 2 * LMAX> edges;
     std::array<double, LMAX> cost;
@@ -225,16 +227,22 @@ static_assert(PLANE_SKEW_BYTES % 256 == 0, "planes stay 256-byte aligned");
 
 int row_pitch(int n) { return (n + 63) / 64 * 64; }
 
-int64_t plane_elems(int m, int n, int esz) { return (int64_t)m * row_pitch(n) + PLANE_SKEW_BYTES / esz; }
+int64_t plane_elems(int m, int n, int esz, int p = 1)
+{
+    return (int64_t)p * m * row_pitch(n) + PLANE_SKEW_BYTES / esz;
+}
+
+// flux components per channel: (u_x, u_y), and u_z on a 3-D grid
+int ucomp(const Resolved &r) { return r.p > 1 ? 3 : 2; }
 
 // The step kernels reach all planes of a field (phi, u, w or f) from one
 // row through a buffer descriptor with 32-bit byte offsets: every field must
 // stay below 2 GiB.
 bool fields_fit(const Resolved &r)
 {
-    const int64_t planes = std::max(2 * r.k, std::max(r.lb, 1));
+    const int64_t planes = std::max(ucomp(r) * r.k, std::max(r.lb, 1));
     const int esz = r.dtype == OMT_F64 ? 8 : 4;
-    return planes * plane_elems(r.m, r.n, esz) * esz < ((int64_t)1 << 31);
+    return planes * plane_elems(r.m, r.n, esz, r.p) * esz < ((int64_t)1 << 31);
 }
 
 omt_status resolve(const omt_params *p, Resolved &r)
@@ -256,6 +264,8 @@ omt_status resolve(const omt_params *p, Resolved &r)
     if (p->dtype != OMT_F32 && p->dtype != OMT_F64) return fail(OMT_EINVAL, "unknown dtype %d", p->dtype);
     if (p->tblock < 0 || p->rows_per_wave < 0) return fail(OMT_EINVAL, "tblock and rows_per_wave must be >= 0");
     if (!(p->reg_eps >= 0.0) || !std::isfinite(p->reg_eps)) return fail(OMT_EINVAL, "reg_eps must be finite and >= 0");
+    if (p->p < 0) return fail(OMT_EINVAL, "depth p must be >= 0 (got %d)", p->p);
+    if ((int64_t)p->m * p->n * std::max(p->p, 1) > (int64_t)1 << 31) return fail(OMT_EINVAL, "grid too large");
 
     r.m = p->m;
     r.n = p->n;
@@ -306,7 +316,8 @@ omt_status resolve(const omt_params *p, Resolved &r)
     r.comp = (p->flags & OMT_FLAG_COMPENSATED_PHI) && p->dtype == OMT_F32;
     r.tblock = p->tblock;
     r.rows = p->rows_per_wave;
-    r.h = p->h > 0.0 ? p->h : 1.0 / double(std::max(r.m, r.n) - 1);
+    r.p = std::max(p->p, 1);
+    r.h = p->h > 0.0 ? p->h : 1.0 / double(std::max(std::max(r.m, r.n), r.p) - 1);
 
     // lambda_max(-Delta_G), -Delta_G = D diag(1/c^2) D^T (Sec. 3.1)
     r.lmax = 0.0;
@@ -323,14 +334,16 @@ omt_status resolve(const omt_params *p, Resolved &r)
         jacobi_eigenvalues(A, r.k, ev);
         for (int c = 0; c < r.k; ++c) r.lmax = std::max(r.lmax, ev[c]);
     }
-    // step sizes of Sec. 7.1 / 7.2 unless given
+    // step sizes of Sec. 7.1 / 7.2 unless given; on a 3-D grid the bound
+    // 8/h^2 of the 2-D Laplacian becomes 12/h^2 and the rule scales with it
     const double h2 = r.h * r.h;
-    r.mu = p->mu > 0.0 ? p->mu : (r.l == 0 ? h2 / (16.0 * r.tau) : h2 / (32.0 * r.tau));
+    const double lx = r.p > 1 ? 12.0 : 8.0;
+    r.mu = p->mu > 0.0 ? p->mu : (r.l == 0 ? h2 / (2.0 * lx * r.tau) : h2 / (4.0 * lx * r.tau));
     r.nu = r.l == 0 ? 0.0 : (p->nu > 0.0 ? p->nu : 1.0 / (4.0 * r.tau * r.lmax));
     if (p->mu > 0.0 || p->nu > 0.0) {
-        const double cond = r.tau * r.mu * 8.0 / h2 + r.tau * r.nu * r.lmax;
+        const double cond = r.tau * r.mu * lx / h2 + r.tau * r.nu * r.lmax;
         if (!(cond < 1.0))
-            return fail(OMT_ESTEP, "tau mu 8/h^2 + tau nu lambda_max = %g must be < 1 (Sec. 7.2)", cond);
+            return fail(OMT_ESTEP, "tau mu %g/h^2 + tau nu lambda_max = %g must be < 1 (Sec. 7.2)", lx, cond);
     }
     // mass classes: connected components of the channel graph
     for (int c = 0; c < r.k; ++c) r.cls[c] = c;
@@ -353,8 +366,14 @@ omt_status resolve(const omt_params *p, Resolved &r)
         r.cls[c] = map[r.cls[c]];
     }
     if (!fields_fit(r))
-        return fail(OMT_EUNSUPPORTED, "a field of %d x %d x %d %s values exceeds 2 GiB", r.m, r.n,
-                    std::max(2 * r.k, r.lb), r.dtype == OMT_F64 ? "FP64" : "FP32");
+        return fail(OMT_EUNSUPPORTED, "a field of %d x %d x %d x %d %s values exceeds 2 GiB", r.m, r.n, r.p,
+                    std::max(ucomp(r) * r.k, r.lb), r.dtype == OMT_F64 ? "FP64" : "FP32");
+    if (r.p > 1) {
+        if (!step3_supported(r.dtype, r.k, r.gk, r.lb))
+            return fail(OMT_EUNSUPPORTED, "3-D grids are compiled for k = 1, 2, 3 (k = %d, %d edges)", r.k, r.l);
+        if (r.comp) return fail(OMT_EUNSUPPORTED, "3-D grids have no compensated potential");
+        if (r.tblock > 1) return fail(OMT_EUNSUPPORTED, "3-D grids run one iteration per launch");
+    }
     return OMT_OK;
 }
 
@@ -379,7 +398,7 @@ Layout make_layout(const Resolved &r)
     Layout L;
     L.esz = r.dtype == OMT_F64 ? 8 : 4;
     L.pitch = row_pitch(r.n);
-    L.plane = plane_elems(r.m, r.n, int(L.esz));
+    L.plane = plane_elems(r.m, r.n, int(L.esz), r.p);
     const size_t pb = align256(size_t(L.plane) * L.esz);
     size_t o = 0;
     L.off_f = o;
@@ -390,7 +409,7 @@ Layout make_layout(const Resolved &r)
     }
     for (int b = 0; b < 2; ++b) {
         L.off_u[b] = o;
-        o += pb * 2 * r.k;
+        o += pb * ucomp(r) * r.k;
     }
     for (int b = 0; b < 2; ++b) {
         L.off_w[b] = o;
@@ -402,7 +421,7 @@ Layout make_layout(const Resolved &r)
         o += r.comp ? pf * r.k : 0;
     }
     L.off_part = o;
-    const size_t met_tiles = size_t((r.n + WAVE - 1) / WAVE) * size_t((r.m + MET_ROWS - 1) / MET_ROWS);
+    const size_t met_tiles = size_t((r.n + WAVE - 1) / WAVE) * size_t((r.m + MET_ROWS - 1) / MET_ROWS) * size_t(r.p);
     size_t npart = std::max<size_t>(size_t(METRIC_BLOCKS_MAX) * KMAX, size_t(SUM_BLOCKS_MAX) * (4 * KMAX + 1));
     npart = std::max(npart, met_tiles * NMET);
     o += align256(sizeof(double) * npart);
@@ -508,6 +527,63 @@ void fill_args(StepArgs<R> &a, const omt_ctx *h, int ci, int co, int wi, int wo,
     }
 }
 
+// Step arguments of a 3-D launch reading buffers (ci, wi), writing (co, wo):
+// zch slices per wave.
+template <typename R>
+void fill_args3(Step3Args<R> &a, const omt_ctx *h, int ci, int co, int wi, int wo, int zch)
+{
+    const Resolved &r = h->r;
+    a.phi_in = static_cast<const R *>(h->phi[ci]);
+    a.phi_out = static_cast<R *>(h->phi[co]);
+    a.u_in = static_cast<const R *>(h->u[ci]);
+    a.u_out = static_cast<R *>(h->u[co]);
+    a.w_in = static_cast<const R *>(h->w[wi]);
+    a.w_out = static_cast<R *>(h->w[wo]);
+    a.f = static_cast<const R *>(h->f);
+    a.plane = h->L.plane;
+    a.m = r.m;
+    a.n = r.n;
+    a.p = r.p;
+    a.pitch = h->L.pitch;
+    a.l = r.l;
+    a.unorm = r.unorm;
+    a.wnorm = r.wnorm;
+    a.ncolw = (r.n + G3_COLS - 1) / G3_COLS;
+    a.nroww = (r.m + G3_ROWS - 1) / G3_ROWS;
+    a.zch = std::max(1, std::min(zch, r.p));
+    a.nzw = (r.p + a.zch - 1) / a.zch;
+    const int64_t waves = int64_t(a.ncolw) * a.nroww * a.nzw;
+    a.nwg = int((waves + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG);
+    a.mu = R(r.mu);
+    a.mu_h = R(r.mu / r.h);
+    a.nu = R(r.nu);
+    a.anu = R(r.alpha * r.nu);
+    a.tau = R(r.tau);
+    a.inv_h = R(1.0 / r.h);
+    a.ureg = R(1.0 / (1.0 + 2.0 * r.mu * r.eps));
+    a.wreg = R(1.0 / (1.0 + 2.0 * r.nu * r.eps));
+    for (int q = 0; q < KMAX * LMAX; ++q) a.gm[q] = R(0);
+    for (int q = 0; q < LMAX; ++q) a.ic[q] = R(0);
+    for (int e = 0; e < r.l; ++e) {
+        a.ic[e] = R(1.0 / r.cost[e]);
+        a.gm[r.edges[2 * e] * LMAX + e] = R(1.0 / r.cost[e]);
+        a.gm[r.edges[2 * e + 1] * LMAX + e] = R(-1.0 / r.cost[e]);
+    }
+}
+
+// Slices per wave on a 3-D grid: enough z chunks that about two waves per
+// SIMD are resident (each chunk recomputes one extra slice, so no more).
+int rule_zch(const omt_ctx *h)
+{
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus < 1)
+        cus = 256;
+    const int64_t tiles = int64_t((h->r.n + G3_COLS - 1) / G3_COLS) * ((h->r.m + G3_ROWS - 1) / G3_ROWS);
+    const int64_t want = int64_t(cus) * 4 * 2;
+    const int64_t nz = std::max<int64_t>(1, std::min<int64_t>(h->r.p, (want + tiles - 1) / tiles));
+    return int((h->r.p + nz - 1) / nz);
+}
+
 // Output columns of one wavefront: 64 aligned columns at one iteration per
 // launch, 64 - 2T (plus halo lanes) when T iterations are pipelined.
 int strip_cols(int T) { return T == 1 ? WAVE : WAVE - 2 * T; }
@@ -518,6 +594,7 @@ int default_rows(const omt_ctx *h, int T)
 {
     if (h->r.rows > 0) return h->r.rows;
     if (h->tuned_rows > 0 && h->tuned_T == T) return h->tuned_rows;
+    if (h->r.p > 1) return rule_zch(h);
     return rule_rows(h, T);
 }
 
@@ -558,6 +635,28 @@ omt_status step_launch(omt_ctx *h, int T, int rows, bool w_inplace, hipStream_t 
 {
     if (!stream) stream = h->stream;
     const Resolved &r = h->r;
+    if (r.p > 1) {
+        // 3-D grids: one iteration per launch, rows = slices per wave; the
+        // halo lanes and rows never read w, so w may be updated in place
+        if (T != 1 || check)
+            return fail(OMT_EUNSUPPORTED, "3-D grids run one iteration per launch (asked for T = %d)", T);
+        const int wo = w_inplace ? h->wcur : 1 - h->wcur;
+        hipError_t e;
+        if (r.dtype == OMT_F64) {
+            Step3Args<double> a;
+            fill_args3(a, h, h->cur, 1 - h->cur, h->wcur, wo, rows);
+            e = launch_step3(r.dtype, r.k, r.gk, r.lb, &a, stream);
+        } else {
+            Step3Args<float> a;
+            fill_args3(a, h, h->cur, 1 - h->cur, h->wcur, wo, rows);
+            e = launch_step3(r.dtype, r.k, r.gk, r.lb, &a, stream);
+        }
+        if (e != hipSuccess) return fail(OMT_EDEVICE, "3-D step launch: %s", hipGetErrorString(e));
+        h->cur = 1 - h->cur;
+        if (!w_inplace) h->wcur = 1 - h->wcur;
+        h->iters_done += 1;
+        return OMT_OK;
+    }
     if (!step_supported(r.dtype, r.k, r.gk, r.lb, T, r.comp))
         return fail(OMT_EUNSUPPORTED, "no step kernel for dtype %d, k %d, graph kind %d (%d edges), T %d%s", r.dtype,
                     r.k, r.gk, r.lb, T, r.comp ? ", compensated" : "");
@@ -599,6 +698,36 @@ omt_status run_metrics(omt_ctx *h, int old_c, int new_c, int old_w, int new_w, h
 {
     if (!stream) stream = h->stream;
     const Resolved &r = h->r;
+    if (r.p > 1) {
+        const int ncolw = (r.n + WAVE - 1) / WAVE;
+        const int ntiles = ncolw * ((r.m + MET_ROWS - 1) / MET_ROWS) * r.p;
+        Metrics3Launch Lm;
+        Lm.dtype = r.dtype;
+        Lm.k = r.k;
+        Lm.gk = r.gk;
+        Lm.lb = r.lb;
+        Lm.alpha = r.alpha;
+        Lm.eps = r.eps;
+        Lm.ncolw = ncolw;
+        Lm.ntiles = ntiles;
+        Lm.partials = h->part;
+        Lm.stream = stream;
+        hipError_t e;
+        if (r.dtype == OMT_F64) {
+            Step3Args<double> a;
+            fill_args3(a, h, old_c, new_c, old_w, new_w, 1);
+            Lm.args = &a;
+            e = launch_metrics3(Lm);
+        } else {
+            Step3Args<float> a;
+            fill_args3(a, h, old_c, new_c, old_w, new_w, 1);
+            Lm.args = &a;
+            e = launch_metrics3(Lm);
+        }
+        if (e != hipSuccess) return fail(OMT_EDEVICE, "3-D metrics launch: %s", hipGetErrorString(e));
+        HIP_TRY(launch_reduce_tiles(h->part, ntiles, h->res, stream));
+        return OMT_OK;
+    }
     const int ncolw = (r.n + WAVE - 1) / WAVE;
     const int ntiles = ncolw * ((r.m + MET_ROWS - 1) / MET_ROWS);
     StepLaunch Lc;
@@ -650,6 +779,7 @@ void fill_info(omt_ctx *h, const double *met, omt_info *info)
 
 int tblock_of(const omt_ctx *h)
 {
+    if (h->r.p > 1) return 1;
     if (h->r.tblock > 0) return h->r.tblock;
     if (h->tuned_T > 0) return h->tuned_T;
     // untuned: two iterations per HBM pass where single-iteration strips
@@ -777,7 +907,7 @@ omt_status enqueue_interval(omt_ctx *h, int64_t nblk, int T, int rowsT, int rows
         if ((s = step_launch(h, 1, rows1, true, stream)) != OMT_OK) return s;
         --rest;
     }
-    if (check_compiled(h->r.gk)) return check_launch(h, rows1, stream);
+    if (h->r.p == 1 && check_compiled(h->r.gk)) return check_launch(h, rows1, stream);
     const int oc = h->cur, ow = h->wcur;
     if ((s = step_launch(h, 1, rows1, false, stream)) != OMT_OK) return s;
     return run_metrics(h, oc, h->cur, ow, h->wcur, stream);
@@ -1046,7 +1176,7 @@ omt_status setup_ctx(omt_ctx *h, const Resolved &r, const void *rho0, const void
     h->cur = h->wcur = 0;
     h->iters_done = 0;
     h->have_last = false;
-    const int64_t npix = (int64_t)r.m * r.n;
+    const int64_t npix = (int64_t)r.m * r.n * r.p;
     h->metric_blocks = int(std::min<int64_t>(METRIC_BLOCKS_MAX, (npix + 255) / 256));
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return fail(OMT_EDEVICE, "set-up: %s", hipGetErrorString(e));
@@ -1094,6 +1224,7 @@ omt_status setup_ctx(omt_ctx *h, const Resolved &r, const void *rho0, const void
     fa.rho1 = rho1;
     fa.dtype = r.dtype;
     fa.m = r.m;
+    fa.p = r.p;
     fa.n = r.n;
     fa.k = r.k;
     fa.pitch = L.pitch;
@@ -1151,7 +1282,7 @@ omt_status omt_grad(omt_handle h, void *d_rho0, void *d_rho1)
     pa.phi = h->phi[h->cur];
     pa.plo = r.comp ? h->plo[h->cur] : nullptr;
     pa.dtype = r.dtype;
-    pa.m = r.m;
+    pa.m = r.m * r.p;  // the plane's rows: every (slice, row) of a 3-D grid
     pa.n = r.n;
     pa.k = r.k;
     pa.pitch = h->L.pitch;
@@ -1166,7 +1297,7 @@ omt_status omt_grad(omt_handle h, void *d_rho0, void *d_rho1)
     for (int c = 0; c < r.k; ++c) {
         if (r.cls[c] < 0) continue;
         cs[r.cls[c]] += h->host[c];
-        cn[r.cls[c]] += double(r.m) * r.n;
+        cn[r.cls[c]] += double(r.m) * r.n * r.p;
     }
     for (int c = 0; c < r.k; ++c) h->host[c] = r.cls[c] < 0 ? 0.0 : cs[r.cls[c]] / cn[r.cls[c]];
     HIP_TRY(hipMemcpyAsync(h->vec, h->host, sizeof(double) * r.k, hipMemcpyHostToDevice, h->stream));
@@ -1176,6 +1307,7 @@ omt_status omt_grad(omt_handle h, void *d_rho0, void *d_rho1)
     xa.plo_out = nullptr;
     xa.dtype = r.dtype;
     xa.m = r.m;
+    xa.p = r.p;
     xa.n = r.n;
     xa.k = r.k;
     xa.pitch = h->L.pitch;
@@ -1204,6 +1336,7 @@ omt_status omt_get_state(omt_handle h, void *phi, void *u, void *w)
     std::memset(&xa, 0, sizeof(xa));
     xa.dtype = r.dtype;
     xa.m = r.m;
+    xa.p = r.p;
     xa.n = r.n;
     xa.pitch = h->L.pitch;
     xa.plane = h->L.plane;
@@ -1243,6 +1376,7 @@ omt_status omt_set_state(omt_handle h, const void *phi, const void *u, const voi
     std::memset(&xa, 0, sizeof(xa));
     xa.dtype = r.dtype;
     xa.m = r.m;
+    xa.p = r.p;
     xa.n = r.n;
     xa.pitch = h->L.pitch;
     xa.plane = h->L.plane;
@@ -1335,7 +1469,7 @@ omt_status omt_autotune(omt_handle h, int32_t iters_per_trial, int32_t *best_t, 
     if (!h) return fail(OMT_EINVAL, "handle is NULL");
     const Resolved &r = h->r;
     const size_t pb = align256(size_t(h->L.plane) * h->L.esz), pf = align256(size_t(h->L.plane) * 4);
-    const size_t n_phi = pb * r.k, n_u = pb * 2 * r.k, n_w = pb * r.l, n_lo = r.comp ? pf * r.k : 0;
+    const size_t n_phi = pb * r.k, n_u = pb * ucomp(r) * r.k, n_w = pb * r.l, n_lo = r.comp ? pf * r.k : 0;
     const size_t total = n_phi + n_u + n_w + n_lo;
     char *snap = nullptr;
     HIP_TRY(hipMalloc(&snap, total));  // temporary copy of the state (freed below)
@@ -1381,14 +1515,15 @@ omt_status omt_autotune(omt_handle h, int32_t iters_per_trial, int32_t *best_t, 
     const int Ts[] = {1, 2, 4, 8};
     for (int T : Ts) {
         if (e != hipSuccess || st != OMT_OK) break;
-        if (!step_supported(r.dtype, r.k, r.gk, r.lb, T, r.comp)) continue;
+        if (r.p > 1 ? T != 1 : !step_supported(r.dtype, r.k, r.gk, r.lb, T, r.comp)) continue;
         // a fixed ladder plus the one-round rule's rows and their neighbours
+        // (on a 3-D grid: slices per wave and the rule's choice)
         std::vector<int> Rs = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
-        const int rr = rule_rows(h, T);
+        const int rr = r.p > 1 ? rule_zch(h) : rule_rows(h, T);
         for (int d = -2; d <= 2; ++d)
             if (rr + d >= 1 && std::find(Rs.begin(), Rs.end(), rr + d) == Rs.end()) Rs.push_back(rr + d);
         for (int rows : Rs) {
-            if (rows > r.m && rows != 2) continue;
+            if (rows > (r.p > 1 ? r.p : r.m) && rows != 2) continue;
             if ((e = restore()) != hipSuccess) break;
             double us = 0.0;
             if ((st = omt_time_steps(h, T, rows, T, &us)) != OMT_OK) break;  // warm-up launch

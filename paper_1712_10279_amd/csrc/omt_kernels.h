@@ -191,6 +191,7 @@ struct MakeFArgs {
     const void *rho0, *rho1;
     int dtype;
     int m, n, k, pitch;
+    int p;                // slices of a 3-D grid (1: 2-D); plane row z m + i
     int64_t plane;
     const double *shift;  // k values subtracted from rho1 - rho0 (device)
     void *f;
@@ -215,6 +216,7 @@ hipError_t launch_plane_sums(const PlaneSumArgs &a, hipStream_t s);
 // SoA <-> AoS copies.  mode: 0 potential out (dst = sign * (phi - mean[c])),
 // 1 u out, 2 w out, 3 phi in, 4 u in (ghosts zeroed), 5 w in.
 struct XferArgs {
+    int p = 1;              // slices of a 3-D grid (1: 2-D); u then has 3 components
     const void *src;
     void *dst;
     const float *plo;       // compensated low part (potential out only)

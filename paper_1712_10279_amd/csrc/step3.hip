@@ -1,0 +1,424 @@
+// Fused PDHG iteration of the vector-OMT method (Sec. 7.2) on 3-D grids,
+// for gfx950.  The paper leaves 3-D imaging as future work (Sec. 8.2); the
+// discretisation is App. A's along each of the three axes: u has three
+// components per channel, u_x between i and i+1, u_y between j and j+1, u_z
+// between z and z+1, with the ghost components u_x(m-1,.,.), u_y(.,n-1,.),
+// u_z(.,.,p-1) zero.
+//
+// One wavefront owns a register tile of G3_ROWS rows by 64 columns and
+// marches it through a chunk of slices along z.  Lanes are columns (every
+// access is a coalesced row segment); lanes 0 and 63 are halo lanes that
+// only supply neighbours, so a wave stores 62 columns.  The tile carries one
+// halo row above (its flux update gives the u_x neighbour of the first row)
+// and one below (its potential gives the gradient of the last row).  The
+// u_z neighbour of a slice is the previous slice's, kept in registers; a
+// chunk starts one slice early to compute it.  Every pixel is computed by
+// the same expressions wherever it sits in a tile, so any tiling gives the
+// same iterates bit for bit.
+
+#include <type_traits>
+
+#include "grid3.h"
+#include "step_device.h"
+
+namespace omt {
+namespace {
+
+using namespace dev;
+
+// Shrink of the flux block of one pixel, (u_x, u_y, u_z) of k channels
+// (App. B): per channel on the spatial 3-vector (u norm 0), element-wise
+// (1), or one block of all 3k components (2).
+template <typename R, int K>
+__device__ __forceinline__ void shrink3(int unorm, R (&x)[K], R (&y)[K], R (&z)[K], R t)
+{
+    if (unorm == 0) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const R s = shrink_scale<R>(sqrt(x[c] * x[c] + y[c] * y[c] + z[c] * z[c]), t);
+            x[c] = x[c] * s;
+            y[c] = y[c] * s;
+            z[c] = z[c] * s;
+        }
+    } else if (unorm == 1) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            x[c] = x[c] * shrink_scale<R>(fabs(x[c]), t);
+            y[c] = y[c] * shrink_scale<R>(fabs(y[c]), t);
+            z[c] = z[c] * shrink_scale<R>(fabs(z[c]), t);
+        }
+    } else {
+        R r2 = R(0);
+#pragma unroll
+        for (int c = 0; c < K; ++c) r2 = r2 + x[c] * x[c];
+#pragma unroll
+        for (int c = 0; c < K; ++c) r2 = r2 + y[c] * y[c];
+#pragma unroll
+        for (int c = 0; c < K; ++c) r2 = r2 + z[c] * z[c];
+        const R s = shrink_scale<R>(sqrt(r2), t);
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            x[c] = x[c] * s;
+            y[c] = y[c] * s;
+            z[c] = z[c] * s;
+        }
+    }
+}
+
+template <typename R, int K, int GK, int L>
+__global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(const Step3Args<R> a)
+{
+    constexpr int LA = L > 0 ? L : 1;
+    constexpr int RT = G3_ROWS;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int g = xcd_remap(blockIdx.x, a.nwg) * STEP_WAVES_PER_WG + int(threadIdx.x / WAVE);
+    if (g >= a.ncolw * a.nroww * a.nzw) return;  // whole wave leaves; no barriers follow
+    const int wc = __builtin_amdgcn_readfirstlane(g % a.ncolw);
+    const int wr = __builtin_amdgcn_readfirstlane((g / a.ncolw) % a.nroww);
+    const int wz = __builtin_amdgcn_readfirstlane(g / (a.ncolw * a.nroww));
+
+    const int j = wc * G3_COLS - 1 + lane;
+    const bool jin = j >= 0 && j < a.n;
+    const bool jst = jin && lane >= 1 && lane <= G3_COLS;
+    const bool last_col = j == a.n - 1;
+    const int i0 = wr * RT;
+    const int z0 = wz * a.zch, z1 = min(z0 + a.zch, a.p);
+    const int zs = max(z0 - 1, 0);
+    const int64_t P = a.plane;
+    const unsigned Psz = unsigned(P) * unsigned(sizeof(R));
+    const unsigned voff = jin ? unsigned(j) * unsigned(sizeof(R)) : OFF_NONE;
+    const unsigned soff = jst ? voff : OFF_NONE;  // stores, and the transfer loads of stored lanes only
+    const int nb_phi = field_bytes(K, P, a.n, sizeof(R)), nb_u = field_bytes(3 * K, P, a.n, sizeof(R));
+    const int nb_w = field_bytes(a.l, P, a.n, sizeof(R));
+    auto roff = [&](int z, int i) -> int64_t { return ((int64_t)z * a.m + i) * a.pitch; };
+    auto row_ok = [&](int i) { return i >= 0 && i < a.m; };
+
+    // potential of the current slice and of the next, rows i0 - 1 .. i0 + RT
+    R pc[RT + 2][K], pn[RT + 2][K];
+    R carry[RT][K];  // 2 u_z' - u_z of the previous slice, tile rows
+#pragma unroll
+    for (int q = 0; q < RT; ++q)
+#pragma unroll
+        for (int c = 0; c < K; ++c) carry[q][c] = R(0);
+#pragma unroll
+    for (int q = 0; q < RT + 2; ++q) {
+        const int i = i0 - 1 + q;
+        const auto rp = row_rsrc(a.phi_in, roff(zs, i), row_ok(i), nb_phi);
+#pragma unroll
+        for (int c = 0; c < K; ++c) pc[q][c] = buf_ld<R>(rp, voff + unsigned(c) * Psz);
+    }
+
+    for (int z = zs; z < z1; ++z) {
+        const bool inner = z >= z0;  // a slice this wave stores (else the halo slice)
+        const bool zlast = z == a.p - 1;
+#pragma unroll
+        for (int q = 0; q < RT + 2; ++q) {
+            const int i = i0 - 1 + q;
+            const auto rp = row_rsrc(a.phi_in, roff(z + 1, i), row_ok(i) && z + 1 < a.p, nb_phi);
+#pragma unroll
+            for (int c = 0; c < K; ++c) pn[q][c] = buf_ld<R>(rp, voff + unsigned(c) * Psz);
+        }
+        R ux[RT + 1][K], uy[RT + 1][K], uz[RT + 1][K];
+#pragma unroll
+        for (int q = 0; q < RT + 1; ++q) {
+            const int i = i0 - 1 + q;
+            const auto ru = row_rsrc(a.u_in, roff(z, i), row_ok(i), nb_u);
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                ux[q][c] = buf_ld<R>(ru, voff + unsigned(c) * Psz);
+                uy[q][c] = buf_ld<R>(ru, voff + unsigned(K + c) * Psz);
+                uz[q][c] = buf_ld<R>(ru, voff + unsigned(2 * K + c) * Psz);
+            }
+        }
+        R wv[RT][LA], fv[RT][K];
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            const int i = i0 + q;
+            const bool ok = row_ok(i) && inner;
+            const auto rw = row_rsrc(a.w_in, roff(z, i), ok && L > 0, nb_w);
+            const auto rf = row_rsrc(a.f, roff(z, i), ok, nb_phi);
+#pragma unroll
+            for (int e = 0; e < LA; ++e) wv[q][e] = L > 0 ? buf_ld<R>(rw, soff + unsigned(e) * Psz) : R(0);
+#pragma unroll
+            for (int c = 0; c < K; ++c) fv[q][c] = buf_ld<R>(rf, voff + unsigned(c) * Psz);
+        }
+
+        R ubxp[K];  // 2 u_x' - u_x of the row above
+#pragma unroll
+        for (int c = 0; c < K; ++c) ubxp[c] = R(0);
+#pragma unroll
+        for (int q = 0; q < RT + 1; ++q) {
+            const int i = i0 - 1 + q;
+            const bool rin = row_ok(i);
+            const bool lane_ok = jin && rin;
+            const bool last_row = i == a.m - 1;
+            // u-update: shrink_u(u + mu grad phi, mu), ghosts zero
+            R tx[K], ty[K], tz[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const R pr = lane_next(pc[q][c]);
+                tx[c] = last_row ? R(0) : ux[q][c] + a.mu_h * (pc[q + 1][c] - pc[q][c]);
+                ty[c] = last_col ? R(0) : uy[q][c] + a.mu_h * (pr - pc[q][c]);
+                tz[c] = zlast ? R(0) : uz[q][c] + a.mu_h * (pn[q][c] - pc[q][c]);
+            }
+            shrink3<R, K>(a.unorm, tx, ty, tz, a.mu);
+            R ubx[K], uby[K], ubz[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                tx[c] = lane_ok ? tx[c] * a.ureg : R(0);
+                ty[c] = lane_ok ? ty[c] * a.ureg : R(0);
+                tz[c] = lane_ok ? tz[c] * a.ureg : R(0);
+                ubx[c] = R(2) * tx[c] - ux[q][c];
+                uby[c] = R(2) * ty[c] - uy[q][c];
+                ubz[c] = R(2) * tz[c] - uz[q][c];
+            }
+            if (q >= 1) {
+                const int r = q - 1;
+                if (inner) {
+                    const bool st = rin;
+                    const int64_t ro = roff(z, i);
+                    const auto rphi = row_rsrc(a.phi_out, ro, st, nb_phi);
+                    const auto ruo = row_rsrc(a.u_out, ro, st, nb_u);
+                    const auto rwo = row_rsrc(a.w_out, ro, st && L > 0, nb_w);
+                    // w-update: shrink_w(w + nu grad_G phi, alpha nu), Sec. 3.1
+                    R wb[LA];
+                    if constexpr (L > 0) {
+                        R wt[LA];
+#pragma unroll
+                        for (int e = 0; e < LA; ++e) {
+                            if constexpr (GK == G_DENSE) {
+                                R s = R(0);
+#pragma unroll
+                                for (int c = 0; c < K; ++c) s = s + a.gm[c * LMAX + e] * pc[q][c];
+                                wt[e] = (e < a.l) ? wv[r][e] + a.nu * s : R(0);
+                            } else {
+                                const int ea = edge_a<GK, K>(e), eb = edge_b<GK, K>(e);
+                                wt[e] = wv[r][e] + a.nu * ((pc[q][ea] - pc[q][eb]) * a.ic[e]);
+                            }
+                        }
+                        shrink_w<R, LA>(a.wnorm, wt, a.anu);
+#pragma unroll
+                        for (int e = 0; e < LA; ++e) {
+                            wt[e] = lane_ok ? wt[e] * a.wreg : R(0);
+                            wb[e] = R(2) * wt[e] - wv[r][e];
+                            buf_st<R>(rwo, soff + unsigned(e) * Psz, wt[e]);
+                        }
+                    }
+                    // phi-update: phi + tau (div_x u_bar + div_G w_bar + f)
+#pragma unroll
+                    for (int c = 0; c < K; ++c) {
+                        const R ubl = lane_prev(uby[c]);
+                        const R dx = ((((ubx[c] - ubxp[c]) + uby[c]) - ubl) + (ubz[c] - carry[r][c])) * a.inv_h;
+                        R dg = R(0);
+                        if constexpr (L > 0) {
+#pragma unroll
+                            for (int e = 0; e < LA; ++e) {
+                                if constexpr (GK == G_DENSE) {
+                                    dg = dg + a.gm[c * LMAX + e] * wb[e];
+                                } else {
+                                    if (edge_a<GK, K>(e) == c) dg = dg + a.ic[e] * wb[e];
+                                    if (edge_b<GK, K>(e) == c) dg = dg - a.ic[e] * wb[e];
+                                }
+                            }
+                        }
+                        const R po = lane_ok ? pc[q][c] + a.tau * ((dx - dg) + fv[r][c]) : R(0);
+                        buf_st<R>(rphi, soff + unsigned(c) * Psz, po);
+                        buf_st<R>(ruo, soff + unsigned(c) * Psz, tx[c]);
+                        buf_st<R>(ruo, soff + unsigned(K + c) * Psz, ty[c]);
+                        buf_st<R>(ruo, soff + unsigned(2 * K + c) * Psz, tz[c]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < K; ++c) carry[r][c] = ubz[c];
+            }
+#pragma unroll
+            for (int c = 0; c < K; ++c) ubxp[c] = ubx[c];
+        }
+#pragma unroll
+        for (int q = 0; q < RT + 2; ++q)
+#pragma unroll
+            for (int c = 0; c < K; ++c) pc[q][c] = pn[q][c];
+    }
+}
+
+// ------------------------------------------------------------- the check
+
+// div_G of w' - w (dgd) and of w' (dg1) at channel c: D diag(1/c) applied
+// to the transfers, in edge order (div_G is its negative, Sec. 3.1).
+template <typename R, int K, int GK, int LA>
+__device__ __forceinline__ void graph_div3(const Step3Args<R> &a, int c, const double (&we0)[LA],
+                                           const double (&we1)[LA], double &dgd, double &dg1)
+{
+    dgd = 0.0;
+    dg1 = 0.0;
+#pragma unroll
+    for (int e = 0; e < LA; ++e) {
+        if constexpr (GK == G_DENSE) {
+            dgd += double(a.gm[c * LMAX + e]) * (we1[e] - we0[e]);
+            dg1 += double(a.gm[c * LMAX + e]) * we1[e];
+        } else {
+            if (edge_a<GK, K>(e) == c) {
+                dgd += double(a.ic[e]) * (we1[e] - we0[e]);
+                dg1 += double(a.ic[e]) * we1[e];
+            }
+            if (edge_b<GK, K>(e) == c) {
+                dgd -= double(a.ic[e]) * (we1[e] - we0[e]);
+                dg1 -= double(a.ic[e]) * we1[e];
+            }
+        }
+    }
+}
+
+// Check terms (Sec. 6.1 R^k with 1/nu on the w block, App. A objectives,
+// constraint residual) of one tile: 64 aligned columns by MET_ROWS rows of
+// one slice; every lane adds its column row by row, lanes past the grid
+// add nothing.
+template <typename R, int K, int GK, int L>
+__global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void tile_metrics3_kernel(const Step3Args<R> a, double alpha,
+                                                                                 double eps, int ncolw, int ntiles,
+                                                                                 double *partials)
+{
+    constexpr int LA = L > 0 ? L : 1;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int t = blockIdx.x * STEP_WAVES_PER_WG + __builtin_amdgcn_readfirstlane(int(threadIdx.x / WAVE));
+    if (t >= ntiles) return;
+    const int nrt = (a.m + MET_ROWS - 1) / MET_ROWS;
+    const int wc = t % ncolw, wr = (t / ncolw) % nrt, z = t / (ncolw * nrt);
+    const int j = wc * WAVE + lane;
+    const bool jok = j < a.n;
+    const int i0 = wr * MET_ROWS, i1 = min(i0 + MET_ROWS, a.m);
+    const int64_t P = a.plane;
+    const double inv_h = double(a.inv_h);
+    const R *phi0 = a.phi_in, *phi1 = a.phi_out, *u0 = a.u_in, *u1 = a.u_out, *w0 = a.w_in, *w1 = a.w_out;
+    double v[NMET];
+#pragma unroll
+    for (int q = 0; q < NMET; ++q) v[q] = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        // every lane reads in-bounds addresses (column j < pitch); lanes past
+        // the grid drop their terms
+        const int64_t o = ((int64_t)z * a.m + i) * a.pitch + j;
+        const int64_t oi = i > 0 ? o - a.pitch : o, oj = j > 0 ? o - 1 : o;
+        const int64_t oz = z > 0 ? o - (int64_t)a.m * a.pitch : o;
+        double acc[NMET];
+#pragma unroll
+        for (int q = 0; q < NMET; ++q) acc[q] = 0.0;
+        double we0[LA], we1[LA];
+#pragma unroll
+        for (int e = 0; e < LA; ++e) {
+            const bool on = L > 0 && e < a.l;
+            we0[e] = on ? double(ld_field(&w0[e * P + o])) : 0.0;
+            we1[e] = on ? double(ld_field(&w1[e * P + o])) : 0.0;
+        }
+        double u2 = 0.0, sq = 0.0;
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const double p0 = double(ld_field(&phi0[c * P + o])), p1 = double(ld_field(&phi1[c * P + o]));
+            const double ux0 = i < a.m - 1 ? double(ld_field(&u0[c * P + o])) : 0.0;
+            const double ux1 = i < a.m - 1 ? double(ld_field(&u1[c * P + o])) : 0.0;
+            const double uy0 = j < a.n - 1 ? double(ld_field(&u0[(K + c) * P + o])) : 0.0;
+            const double uy1 = j < a.n - 1 ? double(ld_field(&u1[(K + c) * P + o])) : 0.0;
+            const double uz0 = z < a.p - 1 ? double(ld_field(&u0[(2 * K + c) * P + o])) : 0.0;
+            const double uz1 = z < a.p - 1 ? double(ld_field(&u1[(2 * K + c) * P + o])) : 0.0;
+            const double xl0 = i > 0 ? double(ld_field(&u0[c * P + oi])) : 0.0;
+            const double xl1 = i > 0 ? double(ld_field(&u1[c * P + oi])) : 0.0;
+            const double yl0 = j > 0 ? double(ld_field(&u0[(K + c) * P + oj])) : 0.0;
+            const double yl1 = j > 0 ? double(ld_field(&u1[(K + c) * P + oj])) : 0.0;
+            const double zl0 = z > 0 ? double(ld_field(&u0[(2 * K + c) * P + oz])) : 0.0;
+            const double zl1 = z > 0 ? double(ld_field(&u1[(2 * K + c) * P + oz])) : 0.0;
+            double dgd = 0.0, dg1 = 0.0;
+            if constexpr (L > 0) graph_div3<R, K, GK, LA>(a, c, we0, we1, dgd, dg1);
+            const double fc = double(ld_field(&a.f[c * P + o]));
+            const double dp = p1 - p0;
+            const double dux = ux1 - ux0, duy = uy1 - uy0, duz = uz1 - uz0;
+            const double ddiv = (((dux - (xl1 - xl0)) + duy - (yl1 - yl0)) + duz - (zl1 - zl0)) * inv_h;
+            const double div1 = (((ux1 - xl1) + uy1 - yl1) + uz1 - zl1) * inv_h;
+            acc[0] += dux * dux + duy * duy + duz * duz;
+            acc[2] += dp * dp;
+            acc[3] += dp * (ddiv - dgd);
+            acc[5] += p1 * fc;
+            const double rr = (div1 - dg1) + fc;
+            acc[6] += rr * rr;
+            acc[7] += p1;
+            sq += ux1 * ux1 + uy1 * uy1 + uz1 * uz1;
+            if (a.unorm == 0)
+                acc[4] += sqrt(ux1 * ux1 + uy1 * uy1 + uz1 * uz1);
+            else if (a.unorm == 1)
+                acc[4] += fabs(ux1) + fabs(uy1) + fabs(uz1);
+            else
+                u2 += ux1 * ux1 + uy1 * uy1 + uz1 * uz1;
+        }
+        pixel_terms<LA>(acc, sq, u2, a.unorm, a.wnorm, alpha, eps, L > 0 ? a.l : 0, we0, we1);
+#pragma unroll
+        for (int q = 0; q < NMET; ++q) v[q] += jok ? acc[q] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NMET; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) partials[(int64_t)t * NMET + q] = s;
+    }
+}
+
+template <typename R, int K, int GK, int L>
+hipError_t launch3(const void *args, hipStream_t s)
+{
+    const Step3Args<R> &a = *static_cast<const Step3Args<R> *>(args);
+    hipLaunchKernelGGL((pdhg_step3_kernel<R, K, GK, L>), dim3(a.nwg), dim3(WAVE * STEP_WAVES_PER_WG), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename R, int K, int GK, int L>
+hipError_t met3(const Metrics3Launch &Lc)
+{
+    const Step3Args<R> &a = *static_cast<const Step3Args<R> *>(Lc.args);
+    const int nb = (Lc.ntiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG;
+    hipLaunchKernelGGL((tile_metrics3_kernel<R, K, GK, L>), dim3(nb), dim3(WAVE * STEP_WAVES_PER_WG), 0, Lc.stream, a,
+                       Lc.alpha, Lc.eps, Lc.ncolw, Lc.ntiles, Lc.partials);
+    return hipGetLastError();
+}
+
+// Compiled problem types on 3-D grids: k = 1 without edges, k = 2 with one
+// edge, k = 3 on the path, the triangle or another graph of up to 3 edges.
+template <typename F>
+hipError_t by_type(int dtype, int k, int gk, int lb, F &&f)
+{
+    if (k == 1 && gk == G_NONE && lb == 0) return f(std::integral_constant<int, 0>{});
+    if (k == 2 && gk == G_PATH && lb == 1) return f(std::integral_constant<int, 1>{});
+    if (k == 3 && gk == G_PATH && lb == 2) return f(std::integral_constant<int, 2>{});
+    if (k == 3 && gk == G_COMPLETE && lb == 3) return f(std::integral_constant<int, 3>{});
+    if (k == 3 && gk == G_DENSE && lb == 2) return f(std::integral_constant<int, 4>{});
+    if (k == 3 && gk == G_DENSE && lb == 3) return f(std::integral_constant<int, 5>{});
+    (void)dtype;
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool step3_supported(int dtype, int k, int gk, int lb)
+{
+    return (dtype == 0 || dtype == 1) &&
+           by_type(dtype, k, gk, lb, [](auto) { return hipSuccess; }) == hipSuccess;
+}
+
+hipError_t launch_step3(int dtype, int k, int gk, int lb, const void *args, hipStream_t stream)
+{
+    return by_type(dtype, k, gk, lb, [&](auto ty) -> hipError_t {
+        constexpr int T = decltype(ty)::value;
+        constexpr int K = T == 0 ? 1 : T == 1 ? 2 : 3;
+        constexpr int GK = T == 0 ? G_NONE : (T == 1 || T == 2) ? G_PATH : T == 3 ? G_COMPLETE : G_DENSE;
+        constexpr int L = T == 0 ? 0 : T == 1 ? 1 : T == 2 ? 2 : T == 3 ? 3 : T == 4 ? 2 : 3;
+        return dtype == 1 ? launch3<double, K, GK, L>(args, stream) : launch3<float, K, GK, L>(args, stream);
+    });
+}
+
+hipError_t launch_metrics3(const Metrics3Launch &Lc)
+{
+    return by_type(Lc.dtype, Lc.k, Lc.gk, Lc.lb, [&](auto ty) -> hipError_t {
+        constexpr int T = decltype(ty)::value;
+        constexpr int K = T == 0 ? 1 : T == 1 ? 2 : 3;
+        constexpr int GK = T == 0 ? G_NONE : (T == 1 || T == 2) ? G_PATH : T == 3 ? G_COMPLETE : G_DENSE;
+        constexpr int L = T == 0 ? 0 : T == 1 ? 1 : T == 2 ? 2 : T == 3 ? 3 : T == 4 ? 2 : 3;
+        return Lc.dtype == 1 ? met3<double, K, GK, L>(Lc) : met3<float, K, GK, L>(Lc);
+    });
+}
+
+}  // namespace omt

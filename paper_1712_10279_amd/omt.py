@@ -32,7 +32,7 @@ class Params(C.Structure):
                 ("alpha", C.c_double), ("tau", C.c_double), ("mu", C.c_double), ("nu", C.c_double),
                 ("h", C.c_double), ("unorm", C.c_int32), ("wnorm", C.c_int32), ("dtype", C.c_int32),
                 ("flags", C.c_uint32), ("tblock", C.c_int32), ("rows_per_wave", C.c_int32),
-                ("reg_eps", C.c_double)]
+                ("reg_eps", C.c_double), ("p", C.c_int32)]
 
 
 M_FRO, M_L1, M_NUC = 0, 1, 2
@@ -161,8 +161,9 @@ class Config:
     eps: float = 0.0
 
 
-def make_params(m, n, k, edges, cfg: Config, dtype: int):
-    """(Params, keep-alive arrays) for the C ABI."""
+def make_params(m, n, k, edges, cfg: Config, dtype: int, p: int = 0):
+    """(Params, keep-alive arrays) for the C ABI; p > 1: a 3-D grid of p slices."""
+    depth = p
     e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
     p = Params()
     lib().omt_params_init(C.byref(p))
@@ -177,43 +178,51 @@ def make_params(m, n, k, edges, cfg: Config, dtype: int):
     p.flags = FLAG_COMPENSATED_PHI if cfg.compensated else 0
     p.tblock, p.rows_per_wave = int(cfg.tblock), int(cfg.rows_per_wave)
     p.reg_eps = float(cfg.eps)
+    p.p = int(depth)
     return p, (e, cost)
 
 
-def resolve_params(m, n, k, edges, **kw):
-    """Host-only: validated (h, mu, nu, lambda_max) of a problem (Sec. 7.2)."""
+def resolve_params(m, n, k, edges, depth=0, **kw):
+    """Host-only: validated (h, mu, nu, lambda_max) of a problem (Sec. 7.2);
+    depth > 1: a 3-D grid of that many slices."""
     dtype = F64 if kw.pop("dtype", "f32") in ("f64", F64) else F32
-    p, keep = make_params(m, n, k, edges, Config(**kw), dtype)
+    p, keep = make_params(m, n, k, edges, Config(**kw), dtype, depth)
     out = [C.c_double() for _ in range(4)]
     _check(lib().omt_resolve_params(C.byref(p), *[C.byref(o) for o in out]), "omt_resolve_params")
     return tuple(o.value for o in out)
 
 
-def workspace_bytes(m, n, k, edges, dtype="f32", **kw):
-    p, keep = make_params(m, n, k, edges, Config(**kw), F64 if dtype in ("f64", F64) else F32)
+def workspace_bytes(m, n, k, edges, dtype="f32", depth=0, **kw):
+    p, keep = make_params(m, n, k, edges, Config(**kw), F64 if dtype in ("f64", F64) else F32, depth)
     b = C.c_size_t()
     _check(lib().omt_workspace_bytes(C.byref(p), C.byref(b)), "omt_workspace_bytes")
     return b.value
 
 
 class Solver:
-    """One transport problem on the GPU (omt_create ... omt_destroy)."""
+    """One transport problem on the GPU (omt_create ... omt_destroy).  rho0,
+    rho1: (m, n, k), or (m, n, p, k) for a 3-D grid of p slices."""
 
     def __init__(self, rho0, rho1, edges=None, **kw):
         torch = _torch()
-        if rho0.dim() != 3 or rho0.shape != rho1.shape:
-            raise ValueError("rho0 and rho1 must both be (m, n, k)")
+        if rho0.dim() not in (3, 4) or rho0.shape != rho1.shape:
+            raise ValueError("rho0 and rho1 must both be (m, n, k) or (m, n, p, k)")
         if not (rho0.is_cuda and rho1.is_cuda):
             raise ValueError("rho0 and rho1 must be on the GPU")
         if rho0.dtype not in (torch.float32, torch.float64) or rho1.dtype != rho0.dtype:
             raise ValueError("rho0 and rho1 must share dtype float32 or float64")
         self.dtype = rho0.dtype
-        self.m, self.n, self.k = (int(s) for s in rho0.shape)
+        if rho0.dim() == 4:
+            self.m, self.n, self.p, self.k = (int(s) for s in rho0.shape)
+        else:
+            self.m, self.n, self.k = (int(s) for s in rho0.shape)
+            self.p = 0
+        self.grid = (self.m, self.n, self.p) if self.p else (self.m, self.n)
         self.edges = np.zeros((0, 2), np.int32) if edges is None else np.asarray(edges, np.int32).reshape(-1, 2)
         self.l = int(self.edges.shape[0])
         self.cfg = Config(**kw)
         dt = F64 if self.dtype == torch.float64 else F32
-        self._p, self._keep = make_params(self.m, self.n, self.k, self.edges, self.cfg, dt)
+        self._p, self._keep = make_params(self.m, self.n, self.k, self.edges, self.cfg, dt, self.p)
         nbytes = C.c_size_t()
         _check(lib().omt_workspace_bytes(C.byref(self._p), C.byref(nbytes)), "omt_workspace_bytes")
         self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=rho0.device)
@@ -248,19 +257,20 @@ class Solver:
 
     def grad(self):
         torch = _torch()
-        d0 = torch.empty((self.m, self.n, self.k), dtype=self.dtype, device=self.device)
+        d0 = torch.empty(self.grid + (self.k,), dtype=self.dtype, device=self.device)
         d1 = torch.empty_like(d0)
         _check(lib().omt_grad(self._h, _ptr(d0), _ptr(d1)), "omt_grad")
         return d0, d1
 
     def get_state(self):
+        """phi (grid x k), u (grid x k x 2, or x 3 on a 3-D grid), w (grid x l)."""
         torch = _torch()
-        phi = torch.empty((self.m, self.n, self.k), dtype=self.dtype, device=self.device)
-        u = torch.empty((self.m, self.n, self.k, 2), dtype=self.dtype, device=self.device)
-        w = torch.zeros((self.m, self.n, max(self.l, 1)), dtype=self.dtype, device=self.device)
+        phi = torch.empty(self.grid + (self.k,), dtype=self.dtype, device=self.device)
+        u = torch.empty(self.grid + (self.k, 3 if self.p else 2), dtype=self.dtype, device=self.device)
+        w = torch.zeros(self.grid + (max(self.l, 1),), dtype=self.dtype, device=self.device)
         _check(lib().omt_get_state(self._h, _ptr(phi), _ptr(u), _ptr(w) if self.l else C.c_void_p(0)),
                "omt_get_state")
-        return {"phi": phi, "u": u, "w": w[:, :, : self.l]}
+        return {"phi": phi, "u": u, "w": w[..., : self.l]}
 
     def set_state(self, phi=None, u=None, w=None):
         args = [_ptr(None if t is None else t.contiguous()) for t in (phi, u, w)]
