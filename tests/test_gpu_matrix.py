@@ -205,3 +205,87 @@ def test_matrix_error_paths():
     with pytest.raises(omt.OMTError) as e:
         omt.MatrixSolver(_dev(torch, lam0, True, True), _dev(torch, bad, True, True), L)
     assert e.value.status == omt.EINVAL
+
+
+def _active(st):
+    """Fractions of pixels where the oracle's U (either axis) and W (any
+    edge) are non-zero."""
+    u = (np.abs(st["ux"]) + np.abs(st["uy"])).reshape(st["ux"].shape[0], st["ux"].shape[1], -1).max(-1)
+    w = np.abs(st["w"]).reshape(st["w"].shape[0], st["w"].shape[1], -1).max(-1)
+    return (u > 0).mean(), (w > 0).mean()
+
+
+def _compare_state(st, r, rel):
+    for key in ("phi", "ux", "uy", "w"):
+        a, b = _np(st[key]), r["state"][key]
+        scale = max(np.abs(b).max(), 1e-300)
+        assert np.abs(a - b).max() <= rel * scale, (key, np.abs(a - b).max(), scale)
+        # where the oracle's shrink returned zero the kernel's must too
+        assert np.abs(a[b == 0]).max(initial=0.0) <= rel * scale, key
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("unorm,wnorm", [(MO.FRO, MO.L1), (MO.L1, MO.L1), (MO.FRO, MO.FRO), (MO.L1, MO.FRO)])
+def test_fp64_active_state_matches_oracle(case, unorm, wnorm):
+    """alpha = 0.1, 1200 iterations: U and W are non-zero on most pixels (the
+    test asserts at least 20 % each), so every shrink divides."""
+    torch = cuda()
+    iters = 1200
+    note(f"case: matrix fp64 active {case} unorm {unorm} wnorm {wnorm} {iters} it")
+    s, lam0, lam1, L = _solver(torch, case, alpha=0.1, tau=2.0, unorm=unorm, wnorm=wnorm)
+    info = s.solve(iters, 0.0, 64)
+    r = MO.solve_pair(lam0, lam1, L, alpha=0.1, tau=2.0, unorm=unorm, wnorm=wnorm, max_iters=iters, check_every=64)
+    ua, wa = _active(r["state"])
+    assert ua >= 0.2 and wa >= 0.2, (ua, wa)
+    _compare_state(s.get_state(), r, 1e-9)
+    M, inf = s.distance()
+    assert M == pytest.approx(r["primal"], rel=1e-10)
+    assert info["residual"] == pytest.approx(r["residual"], rel=1e-8)
+    assert inf["dual"] == pytest.approx(r["dual"], rel=1e-8, abs=1e-14)
+    assert inf["mass_residual"] == pytest.approx(r["mass_residual"], rel=1e-8)
+
+
+@pytest.mark.parametrize("case", list(NUC_CASES))
+@pytest.mark.parametrize("unorm,wnorm", [(MO.NUC, MO.NUC), (MO.FRO, MO.NUC), (MO.NUC, MO.L1)])
+def test_fp64_nuclear_active_state_matches_oracle(case, unorm, wnorm):
+    """Nuclear norms at alpha = 0.1, 150 iterations, U and W active on at
+    least 20 % of pixels each."""
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    m, n, k, real, L = NUC_CASES[case]
+    iters = 150
+    note(f"case: matrix fp64 nuclear active {case} unorm {unorm} wnorm {wnorm} {iters} it")
+    lam0, lam1 = I.matrix_pair(6, m, n, k, real)
+    s = omt.MatrixSolver(_dev(torch, lam0, real, True), _dev(torch, lam1, real, True), L, alpha=0.1, tau=2.0,
+                         unorm=unorm, wnorm=wnorm)
+    info = s.solve(iters, 0.0, 30)
+    r = MO.solve_pair(lam0, lam1, L, alpha=0.1, tau=2.0, unorm=unorm, wnorm=wnorm, max_iters=iters, check_every=30)
+    ua, wa = _active(r["state"])
+    assert ua >= 0.2 and wa >= 0.2, (ua, wa)
+    _compare_state(s.get_state(), r, 1e-9)
+    M, _ = s.distance()
+    assert M == pytest.approx(r["primal"], rel=1e-10)
+    assert info["residual"] == pytest.approx(r["residual"], rel=1e-8)
+
+
+@pytest.mark.parametrize("case", ["dti_real_k3", "pauli_real_k2", "complex_k2", "dti_plus_one_real_k3"])
+def test_two_iterations_per_pass_bit_identical_when_active(case):
+    """FP32 solves with one and two iterations per launch give the same bits
+    after 1200 iterations at alpha = 0.1, where U and W are non-zero on at
+    least 20 % of pixels; the FP32 distance stays within 1e-4 of the FP64
+    oracle's."""
+    torch = cuda()
+    note(f"case: matrix T=2 bits active {case}")
+    kw = dict(f64=False, alpha=0.1, tau=2.0, unorm=MO.FRO, wnorm=MO.L1)
+    s1, lam0, lam1, L = _solver(torch, case, tblock=1, **kw)
+    s2 = _solver(torch, case, tblock=2, **kw)[0]
+    i1, i2 = s1.solve(1200, 0.0, 64), s2.solve(1200, 0.0, 64)
+    assert i1["residual"] == i2["residual"] and i1["primal"] == i2["primal"]
+    a, b = s1.get_state(), s2.get_state()
+    for key in ("phi", "ux", "uy", "w"):
+        assert torch.equal(a[key], b[key]), (case, key)
+    ua, wa = _active({key: _np(a[key]) for key in ("ux", "uy", "w")})
+    assert ua >= 0.2 and wa >= 0.2, (ua, wa)
+    r = MO.solve_pair(lam0, lam1, L, alpha=0.1, tau=2.0, max_iters=1200, check_every=64)
+    M, _ = s2.distance()
+    assert abs(M - r["primal"]) <= 1e-4 * r["primal"]
