@@ -216,6 +216,21 @@ omt_status omt_batch_get_state(omt_batch_handle h, int32_t b, void *phi, void *u
 /* Warm start of problem b of the batch (as omt_set_state; Sec. 7.2 takes
  * initial guesses); the next omt_batch_solve continues from it. */
 omt_status omt_batch_set_state(omt_batch_handle h, int32_t b, const void *phi, const void *u, const void *w);
+/* Choose the rows per strip of the batched step kernel for every shape class
+ * of the batch (problems with the same grid and compiled type): each
+ * candidate is timed over launches_per_trial launches (at least 4, HIP
+ * events on the batch's private stream) of that class alone, reading the
+ * current iterates without changing them.  Problems whose rows_per_wave the
+ * caller fixed keep it.  The choice is kept in the handle (the next
+ * omt_batch_solve uses it) and in the tuning cache under "batch <class>"
+ * (OMT_TUNE_CACHE), where omt_batch_create finds it.  Rows never change the
+ * iterates: every problem stays bit-identical to its own omt_solve.
+ * rows: host array of B (nullable), the rows chosen per problem;
+ * us_per_iter (nullable): one batched iteration of all B problems with the
+ * chosen rows, in microseconds.  launches_per_trial = 0 tunes nothing and
+ * only reports the rows in use (us_per_iter 0).  Not for use while a solve
+ * of this handle runs on another thread. */
+omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, int32_t *rows, double *us_per_iter);
 omt_status omt_batch_destroy(omt_batch_handle h);
 
 /* ----------------------------------------------------------- utilities */
@@ -232,7 +247,9 @@ omt_status omt_autotune(omt_handle h, int32_t iters_per_trial, int32_t *best_t, 
 /* Launch exactly n iterations of the step kernel with the given blocking
  * depth (T must divide n) and report the mean time per launch in
  * microseconds measured with HIP events on the handle's stream.  For
- * measurement; the state advances by n iterations. */
+ * measurement; the state advances by n iterations.  One more launch,
+ * untimed, precedes them so that the queue is busy when the timed region
+ * opens; it writes only the buffers the first timed launch overwrites. */
 omt_status omt_time_steps(omt_handle h, int32_t T, int32_t rows_per_wave, int64_t n, double *us_per_launch);
 
 /* ------------------------------------------------- without allocation */

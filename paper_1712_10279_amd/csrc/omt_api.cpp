@@ -459,6 +459,7 @@ struct omt_ctx {
     omt_info last;
     bool have_last;
     int tuned_T, tuned_rows;   // from omt_autotune or the tuning cache (0: none)
+    int user_rows;             // rows per wave the caller fixed (0: none); batched problems
     hipStream_t cap;           // private stream for capturing the check interval
     struct Graph {
         hipGraphExec_t exec;
@@ -846,12 +847,11 @@ void tune_cache_load(omt_ctx *h)
         }
 }
 
-void tune_cache_store(const omt_ctx *h, int T, int rows, double us)
+void tune_cache_store_key(const std::string &key, int T, int rows, double us)
 {
     const char *path = std::getenv("OMT_TUNE_CACHE");
     if (!path) return;
     std::vector<TuneEntry> all = tune_cache_read(path);
-    const std::string key = tune_key(h);
     bool found = false;
     for (TuneEntry &t : all)
         if (t.key == key) {
@@ -871,6 +871,21 @@ void tune_cache_store(const omt_ctx *h, int T, int rows, double us)
     std::fprintf(fp, "}\n");
     std::fclose(fp);
     std::rename(tmp.c_str(), path);
+}
+
+void tune_cache_store(const omt_ctx *h, int T, int rows, double us) { tune_cache_store_key(tune_key(h), T, rows, us); }
+
+// Rows per strip the batched solver's tuner stored for this problem's shape
+// class, or 0.
+int tune_cache_batch_rows(const omt_ctx *h)
+{
+    const char *path = std::getenv("OMT_TUNE_CACHE");
+    if (!path) return 0;
+    const std::string key = "batch " + tune_key(h);
+    int rows = 0;
+    for (const TuneEntry &t : tune_cache_read(path))
+        if (t.key == key && t.T == 1 && t.rows > 0) rows = t.rows;
+    return rows;
 }
 
 // Rows per wave of a check launch: a multiple of MET_ROWS near the step's,
@@ -1422,8 +1437,18 @@ omt_status omt_time_steps(omt_handle h, int32_t T, int32_t rows_per_wave, int64_
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    // an untimed launch first, so that the queue is busy when the timed
+    // region opens: it reads the current iterate and writes the other
+    // buffers (w out of place) without making them current, so the timed
+    // launches start from the caller's state
+    const int c0 = h->cur, w0 = h->wcur;
+    const int64_t it0 = h->iters_done;
+    omt_status s = step_launch(h, T, rows, false);
+    h->cur = c0;
+    h->wcur = w0;
+    h->iters_done = it0;
+    if (s != OMT_OK) return s;
     HIP_TRY(hipEventRecord(e0, h->stream));
-    omt_status s = OMT_OK;
     for (int64_t q = 0; q < n / T && s == OMT_OK; ++q) s = step_launch(h, T, rows, T == 1);
     HIP_TRY(hipEventRecord(e1, h->stream));
     HIP_TRY(hipEventSynchronize(e1));
@@ -1589,6 +1614,8 @@ struct omt_bctx {
     unsigned *d_bar;
     int total_tiles, total_mtiles;  // strips / metric tiles in the current lists
     int full_tiles, full_mtiles;    // ... with every problem in them
+    int cap_tiles;                  // room of the strip list (one row per strip)
+    int resident;                   // workgroups of the persistent kernel the chip holds at once
     bool comp;
     int dtype;
     int nblocks;
@@ -1615,9 +1642,9 @@ int batch_rows_default(int m) { return std::max(2, std::min(8, (m + 31) / 32)); 
 
 struct BatchLayout {
     std::vector<size_t> off, bytes;
-    std::vector<int> ntiles, mtiles, rows;
+    std::vector<int> mtiles;
     size_t off_pairs, off_state, off_tp, off_mtp, off_part, off_bar, total;
-    int total_tiles, total_mtiles;
+    int cap_tiles, total_mtiles;  // strip list sized for one row per strip
 };
 
 omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, bool *comp, int *dtype)
@@ -1625,7 +1652,7 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
     if (B < 1) return fail(OMT_EINVAL, "batch size %d < 1", B);
     if (!params) return fail(OMT_EINVAL, "params is NULL");
     size_t o = 0;
-    L.total_tiles = L.total_mtiles = 0;
+    L.cap_tiles = L.total_mtiles = 0;
     for (int p = 0; p < B; ++p) {
         Resolved r;
         omt_status s = resolve(&params[p], r);
@@ -1641,12 +1668,9 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
         L.off.push_back(o);
         L.bytes.push_back(b);
         o += align256(b);
-        const int rows = r.rows > 0 ? r.rows : batch_rows_default(r.m);
         const int ncolw = (r.n + WAVE - 1) / WAVE;
-        L.rows.push_back(rows);
-        L.ntiles.push_back(ncolw * ((r.m + rows - 1) / rows));
         L.mtiles.push_back(ncolw * ((r.m + MET_ROWS - 1) / MET_ROWS));
-        L.total_tiles += L.ntiles.back();
+        L.cap_tiles += ncolw * r.m;
         L.total_mtiles += L.mtiles.back();
     }
     L.off_pairs = o;
@@ -1654,7 +1678,7 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
     L.off_state = o;
     o += align256(sizeof(BatchPairState) * B);
     L.off_tp = o;
-    o += align256(sizeof(int) * L.total_tiles);
+    o += align256(sizeof(int) * size_t(L.cap_tiles));
     L.off_mtp = o;
     o += align256(sizeof(int) * L.total_mtiles);
     L.off_part = o;
@@ -1741,6 +1765,15 @@ hipError_t batch_set_lists(omt_bctx *h, const std::vector<char> &active)
     // the host vectors go out of scope: finish the copies first
     if (e == hipSuccess) e = hipStreamSynchronize(h->cap);
     return e;
+}
+
+// Workgroups of the persistent schedule: every one resident at once, and no
+// more than the strips keep busy (about two strips per wave): fewer
+// workgroups make the grid barriers cheaper for small batches.
+void batch_size_grid(omt_bctx *h)
+{
+    const int want = (h->full_tiles + 2 * STEP_WAVES_PER_WG - 1) / (2 * STEP_WAVES_PER_WG);
+    h->nblocks = std::max(1, std::min(h->resident, want));
 }
 
 void batch_drop_graphs(omt_bctx *h)
@@ -1876,7 +1909,7 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
     h->ws = static_cast<char *>(workspace);
     h->comp = comp;
     h->dtype = dtype;
-    h->total_tiles = h->full_tiles = L.total_tiles;
+    h->cap_tiles = L.cap_tiles;
     h->total_mtiles = h->full_mtiles = L.total_mtiles;
     h->d_pairs = reinterpret_cast<BatchPair *>(h->ws + L.off_pairs);
     h->d_state = reinterpret_cast<BatchPairState *>(h->ws + L.off_state);
@@ -1895,6 +1928,14 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         }
         h->ctx.push_back(c);
     }
+    // rows per strip: the caller's, else the batched tuner's cached choice
+    // for the problem's shape class, else the default rule
+    for (int p = 0; p < B; ++p) {
+        omt_ctx *c = h->ctx[p];
+        c->user_rows = c->r.rows;
+        if (c->r.rows <= 0) c->r.rows = tune_cache_batch_rows(c);
+        if (c->r.rows <= 0) c->r.rows = batch_rows_default(c->r.m);
+    }
     // problem descriptors and the strip / tile lists
     std::vector<int> tp, mtp;
     h->pairs.resize(B);
@@ -1908,7 +1949,7 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         bp.l = c->r.l;
         bp.ncolw = ncolw;
         bp.tile0 = t0;
-        bp.ntiles = L.ntiles[p];
+        bp.ntiles = ncolw * ((c->r.m + c->r.rows - 1) / c->r.rows);
         bp.mcolw = ncolw;
         bp.mtile0 = m0;
         bp.mtiles = L.mtiles[p];
@@ -1916,11 +1957,12 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         bp.nu = c->r.nu;
         bp.tau = c->r.tau;
         bp.R0 = c->r.tau * c->fnorm2;
-        for (int q = 0; q < L.ntiles[p]; ++q) tp.push_back(p);
+        for (int q = 0; q < bp.ntiles; ++q) tp.push_back(p);
         for (int q = 0; q < L.mtiles[p]; ++q) mtp.push_back(p);
-        t0 += L.ntiles[p];
+        t0 += bp.ntiles;
         m0 += L.mtiles[p];
     }
+    h->total_tiles = h->full_tiles = t0;
     h->st.resize(B);
     hipError_t e = hipMemcpyAsync(h->d_tile_pair, tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
@@ -1940,13 +1982,8 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         destroy_batch(h);
         return fail(OMT_EDEVICE, "batched kernel does not fit on a compute unit");
     }
-    // every workgroup resident at once, and no more workgroups than the
-    // strips keep busy (about two strips per wave): fewer workgroups make the
-    // grid barriers cheaper for small batches
-    const int want = (h->total_tiles + 2 * STEP_WAVES_PER_WG - 1) / (2 * STEP_WAVES_PER_WG);
-    h->nblocks = std::max(1, std::min(bpc * cus, want));
-    // remember the rows per strip in the per-problem arguments
-    for (int p = 0; p < B; ++p) h->ctx[p]->r.rows = L.rows[p];
+    h->resident = bpc * cus;
+    batch_size_grid(h);
     *out = h;
     return OMT_OK;
 }
@@ -2064,6 +2101,122 @@ omt_status omt_batch_set_state(omt_batch_handle h, int32_t b, const void *phi, c
     // the next omt_batch_solve builds its step arguments from the problem's
     // current buffers, which this fills
     return omt_set_state(h->ctx[b], phi, u, w);
+}
+
+omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, int32_t *rows, double *us_per_iter)
+{
+    if (!h) return fail(OMT_EINVAL, "handle is NULL");
+    if (launches_per_trial < 0) return fail(OMT_EINVAL, "launches_per_trial < 0");
+    if (launches_per_trial == 0) {
+        // report the rows in use, tune nothing
+        for (int p = 0; p < h->B && rows; ++p) rows[p] = h->ctx[p]->r.rows;
+        if (us_per_iter) *us_per_iter = 0.0;
+        return OMT_OK;
+    }
+    const int n = std::max(4, int(launches_per_trial));
+    // problems of one shape class (grid, compiled type) share their rows;
+    // problems whose rows the caller fixed keep them
+    std::vector<std::vector<int>> classes;
+    {
+        std::vector<std::string> keys;
+        for (int p = 0; p < h->B; ++p) {
+            const omt_ctx *c = h->ctx[p];
+            if (c->user_rows > 0) continue;
+            char key[64];
+            std::snprintf(key, sizeof(key), "%d %d %d", c->r.m, c->r.n, h->pairs[p].type);
+            const auto it = std::find(keys.begin(), keys.end(), std::string(key));
+            if (it == keys.end()) {
+                keys.emplace_back(key);
+                classes.push_back({p});
+            } else {
+                classes[size_t(it - keys.begin())].push_back(p);
+            }
+        }
+    }
+    BatchArgs ba;
+    ba.pairs = h->d_pairs;
+    ba.state = h->d_state;
+    ba.tile_pair = h->d_tile_pair;
+    ba.mtile_pair = h->d_mtile_pair;
+    ba.partials = h->d_partials;
+    ba.bar = h->d_bar;
+    ba.B = h->B;
+    ba.total_mtiles = h->total_mtiles;
+    ba.check_every = 64;
+    ba.max_iters = 1;
+    ba.tol = 0.0;
+    // the timed launches use variant 1 of the step arguments (read the
+    // current phi, u, w; write phi and u to the other ping-pong buffer and
+    // w out of place), so the current iterates are never changed
+    auto set_rows = [&](int p, int R) {
+        omt_ctx *c = h->ctx[p];
+        BatchPair &bp = h->pairs[p];
+        c->r.rows = R;
+        bp.ntiles = bp.ncolw * ((c->r.m + R - 1) / R);
+        const int nroww = (c->r.m + R - 1) / R, ci = c->cur, wi = c->wcur;
+        if (h->dtype == OMT_F64)
+            fill_args(bp.args_mut<double>(1), c, ci, 1 - ci, wi, 1 - wi, R, bp.ncolw, nroww, 0);
+        else
+            fill_args(bp.args_mut<float>(1), c, ci, 1 - ci, wi, 1 - wi, R, bp.ncolw, nroww, 0);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto timed = [&](const std::vector<char> &active, double *us) -> hipError_t {
+        hipError_t e = batch_set_lists(h, active);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->d_pairs, h->pairs.data(), sizeof(BatchPair) * h->B, hipMemcpyHostToDevice, h->cap);
+        ba.total_tiles = h->total_tiles;
+        if (e == hipSuccess) e = launch_batch_step(ba, h->dtype, h->comp, 1, h->cap);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, h->cap);
+        for (int q = 0; q < n && e == hipSuccess; ++q) e = launch_batch_step(ba, h->dtype, h->comp, 1, h->cap);
+        if (e == hipSuccess) e = hipEventRecord(e1, h->cap);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        *us = 1000.0 * double(ms) / n;
+        return e;
+    };
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    // every problem counts as unfinished while it is timed
+    if (e == hipSuccess) e = launch_zero(h->d_state, sizeof(BatchPairState) * h->B, h->cap);
+    const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
+    for (size_t q = 0; q < classes.size() && e == hipSuccess; ++q) {
+        const std::vector<int> &cls = classes[q];
+        const int m = h->ctx[cls[0]]->r.m;
+        std::vector<char> active(h->B, 0);
+        for (int p : cls) active[p] = 1;
+        int bestR = h->ctx[cls[0]]->r.rows;
+        double best = 1e300;
+        for (int R : cand) {
+            if (R > m && R != 1) continue;
+            for (int p : cls) set_rows(p, R);
+            double us = 0.0;
+            if ((e = timed(active, &us)) != hipSuccess) break;
+            if (us < best) {
+                best = us;
+                bestR = R;
+            }
+        }
+        for (int p : cls) set_rows(p, bestR);
+        tune_cache_store_key("batch " + tune_key(h->ctx[cls[0]]), 1, bestR, best);
+    }
+    // every problem in the lists again, with its tuned rows
+    double all_us = 0.0;
+    if (e == hipSuccess) e = timed(std::vector<char>(h->B, 1), &all_us);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->cap);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(OMT_EDEVICE, "batch autotune: %s", hipGetErrorString(e));
+    h->full_tiles = h->total_tiles;
+    batch_size_grid(h);
+    batch_drop_graphs(h);
+    for (int p = 0; p < h->B; ++p) {
+        h->ctx[p]->have_last = false;
+        if (rows) rows[p] = h->ctx[p]->r.rows;
+    }
+    if (us_per_iter) *us_per_iter = all_us;
+    return OMT_OK;
 }
 
 omt_status omt_batch_destroy(omt_batch_handle h)

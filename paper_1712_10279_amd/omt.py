@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import warnings
 from dataclasses import dataclass
 
 import numpy as np
@@ -84,6 +85,7 @@ _SIGS = {
     "omt_batch_grad": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "omt_batch_get_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "omt_batch_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "omt_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "omt_batch_destroy": (C.c_int, [C.c_void_p]),
     "omt_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]),
@@ -273,10 +275,10 @@ class Solver:
         return {"phi": phi, "u": u, "w": w[..., : self.l]}
 
     def set_state(self, phi=None, u=None, w=None):
-        args = [_ptr(None if t is None else t.contiguous()) for t in (phi, u, w)]
+        """Load phi, u, w (shapes of get_state, the solver's dtype; None keeps
+        that field) as the current iterate."""
         keep = [t.contiguous() if t is not None else None for t in (phi, u, w)]
-        args = [_ptr(t) for t in keep]
-        _check(lib().omt_set_state(self._h, *args), "omt_set_state")
+        _check(lib().omt_set_state(self._h, *[_ptr(t) for t in keep]), "omt_set_state")
 
     def time_steps(self, T, rows_per_wave, n):
         us = C.c_double()
@@ -340,9 +342,9 @@ def _autograd_function():
         """
 
         @staticmethod
-        def forward(ctx, rho0, rho1, edges, max_iters, tol, check_every, kw):
+        def forward(ctx, rho0, rho1, edges, max_iters, tol, check_every, kw, on_notconv):
             s = Solver(rho0.detach(), rho1.detach(), edges, **kw)
-            s.solve(max_iters, tol, check_every)
+            _notconv([s.solve(max_iters, tol, check_every)], tol, on_notconv)
             V, info = s.distance()
             d0, _ = s.grad()
             ctx.save_for_backward(d0)
@@ -352,7 +354,7 @@ def _autograd_function():
         @staticmethod
         def backward(ctx, g):
             (d0,) = ctx.saved_tensors
-            return g * d0, -g * d0, None, None, None, None, None
+            return g * d0, -g * d0, None, None, None, None, None, None
 
     class OMTDistanceBatch(torch.autograd.Function):
         """The same for a batch (B, m, n, k) of pairs solved together by the
@@ -360,11 +362,12 @@ def _autograd_function():
         returns the (B,) distances."""
 
         @staticmethod
-        def forward(ctx, rho0, rho1, edges, max_iters, tol, check_every, kw):
+        def forward(ctx, rho0, rho1, edges, max_iters, tol, check_every, kw, on_notconv):
             probs = [dict(rho0=rho0[b].detach(), rho1=rho1[b].detach(), edges=edges, **kw)
                      for b in range(rho0.shape[0])]
             bs = BatchSolver(probs)
             ctx.infos = bs.solve(max_iters, tol, check_every)
+            _notconv(ctx.infos, tol, on_notconv)
             V = bs.distance()
             d0, _ = bs.grad()
             d0 = torch.stack(d0)
@@ -375,7 +378,7 @@ def _autograd_function():
         def backward(ctx, g):
             (d0,) = ctx.saved_tensors
             gb = g.reshape(-1, 1, 1, 1)
-            return gb * d0, -gb * d0, None, None, None, None, None
+            return gb * d0, -gb * d0, None, None, None, None, None, None
 
     return OMTDistance, OMTDistanceBatch
 
@@ -383,24 +386,48 @@ def _autograd_function():
 _OMT_FN = None
 
 
-def omt_loss(rho0, rho1, edges=None, max_iters=100000, tol=1e-6, check_every=64, **kw):
+class NotConvergedWarning(UserWarning):
+    """A loss value whose solve stopped at max_iters above its tolerance."""
+
+
+def _notconv(infos, tol, on_notconv):
+    if tol <= 0 or on_notconv == "ignore":
+        return
+    bad = [(b, i["iters"], i["residual"]) for b, i in enumerate(infos) if not i["converged"]]
+    if not bad:
+        return
+    text = (f"{len(bad)} of {len(infos)} solves stopped above tol {tol:g} (pair, iterations, R^k): "
+            + ", ".join(f"({b}, {it}, {r:.3g})" for b, it, r in bad[:8]))
+    if on_notconv == "raise":
+        raise OMTError(ENOTCONV, "omt_loss", text)
+    warnings.warn(text, NotConvergedWarning, stacklevel=4)
+
+
+def omt_loss(rho0, rho1, edges=None, max_iters=100000, tol=1e-6, check_every=64, on_notconv="warn", **kw):
     """Differentiable V(rho0, rho1) (see ``OMTDistance``); rho0 / rho1 may be
-    (m, n, k) or a batch (B, m, n, k), which returns a (B,) tensor."""
+    (m, n, k) or a batch (B, m, n, k), which returns a (B,) tensor.
+
+    A solve that reaches max_iters above ``tol`` still gives its value and
+    gradient; ``on_notconv`` says what else happens: "warn" (a
+    NotConvergedWarning naming the pairs), "raise" (OMTError ENOTCONV) or
+    "ignore"."""
     global _OMT_FN
+    if on_notconv not in ("warn", "raise", "ignore"):
+        raise ValueError(f"on_notconv must be warn, raise or ignore, not {on_notconv!r}")
     if _OMT_FN is None:
         _OMT_FN = _autograd_function()
     single, batched = _OMT_FN
     if rho0.dim() == 4:
         torch = _torch()
         try:
-            return batched.apply(rho0, rho1, edges, max_iters, tol, check_every, kw)
+            return batched.apply(rho0, rho1, edges, max_iters, tol, check_every, kw, on_notconv)
         except OMTError as e:
             if e.status != EUNSUPPORTED:
                 raise
         # problems the batched kernel does not compile: one solve per pair
-        return torch.stack([single.apply(rho0[b], rho1[b], edges, max_iters, tol, check_every, kw)
+        return torch.stack([single.apply(rho0[b], rho1[b], edges, max_iters, tol, check_every, kw, on_notconv)
                             for b in range(rho0.shape[0])])
-    return single.apply(rho0, rho1, edges, max_iters, tol, check_every, kw)
+    return single.apply(rho0, rho1, edges, max_iters, tol, check_every, kw, on_notconv)
 
 
 class BatchSolver:
@@ -479,6 +506,15 @@ class BatchSolver:
         _check(lib().omt_batch_get_state(self._h, int(b), _ptr(phi), _ptr(u), _ptr(w) if l else C.c_void_p(0)),
                "omt_batch_get_state")
         return {"phi": phi, "u": u, "w": w[:, :, :l]}
+
+    def autotune(self, launches_per_trial=32):
+        """Rows per strip for every shape class of the batch (see
+        omt_batch_autotune); returns (rows per problem, us per batched
+        iteration of all problems)."""
+        rows = (C.c_int32 * self.B)()
+        us = C.c_double()
+        _check(lib().omt_batch_autotune(self._h, int(launches_per_trial), rows, C.byref(us)), "omt_batch_autotune")
+        return list(rows), us.value
 
     def set_state(self, b, phi=None, u=None, w=None):
         """Warm start of problem b (see Solver.set_state)."""

@@ -165,3 +165,21 @@ def test_static_entry_rejects_oversize_before_device_work():
     assert b"static workspace" in omt.lib().omt_last_error()
     p.k = 0
     assert omt.lib().omt_solve_static(C.byref(p), None, None, 10, 0.0, 64, None, None, None, None, None) == omt.EINVAL
+
+
+def test_loss_reports_unconverged_pairs():
+    """omt_loss's policy for solves that stop above tol (host logic only)."""
+    import warnings
+    ok = {"converged": True, "iters": 64, "residual": 1e-7}
+    bad = {"converged": False, "iters": 128, "residual": 3e-4}
+    omt._notconv([ok, ok], 1e-6, "raise")
+    omt._notconv([ok, bad], 0.0, "raise")          # tol 0: a fixed iteration count, nothing to report
+    omt._notconv([ok, bad], 1e-6, "ignore")
+    with pytest.raises(omt.OMTError) as e:
+        omt._notconv([ok, bad], 1e-6, "raise")
+    assert e.value.status == omt.ENOTCONV and "(1, 128," in str(e.value)
+    with warnings.catch_warnings(record=True) as got:
+        warnings.simplefilter("always")
+        omt._notconv([bad, ok, bad], 1e-6, "warn")
+    assert len(got) == 1 and issubclass(got[0].category, omt.NotConvergedWarning)
+    assert "2 of 3" in str(got[0].message)

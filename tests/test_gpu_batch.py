@@ -130,3 +130,44 @@ def test_batch_rejects_mixed_dtypes():
     probs[1] = dict(probs[1], rho0=probs[1]["rho0"].double(), rho1=probs[1]["rho1"].double())
     with pytest.raises(ValueError):
         omt.BatchSolver(probs)
+
+
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+def test_batch_autotune_keeps_bits_and_caches_rows(mode, tmp_path, monkeypatch):
+    """omt_batch_autotune picks rows per shape class without changing any
+    iterate; the tuned batch stays bit-identical to per-problem solves, a
+    caller's fixed rows are kept, and a new batch takes the tuned rows from
+    the tuning cache."""
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("OMT_TUNE_CACHE", str(cache))
+    dt = torch.float64 if mode == "f64" else torch.float32
+    probs = _problems(torch, 70, dtype=dt)
+    probs[1]["rows_per_wave"] = 3
+    note(f"case: batch autotune {mode}, {len(probs)} problems")
+    b = omt.BatchSolver(probs)
+    b.solve(100, 0.0, 64)
+    before = [b.get_state(q) for q in range(len(probs))]
+    rows, us = b.autotune(8)
+    note(f"  tuned rows {rows}, {us:.2f} us per batched iteration")
+    assert len(rows) == len(probs) and all(r >= 1 for r in rows) and us > 0
+    assert rows[1] == 3
+    for q in range(len(probs)):
+        st = b.get_state(q)
+        for key in ("phi", "u", "w"):
+            assert torch.equal(st[key], before[q][key]), (q, key)
+    infos = b.solve(300, 0.0, 64)
+    for q, pr in enumerate(probs):
+        s, _ = _plain(torch, pr, 100, 0.0)
+        info = s.solve(300, 0.0, 64)
+        gs, bs = s.get_state(), b.get_state(q)
+        for key in ("phi", "u", "w"):
+            assert torch.equal(gs[key], bs[key]), (q, key)
+        assert infos[q]["residual"] == info["residual"]
+    # one cache entry per shape class tuned (problem 1's rows were fixed)
+    assert cache.read_text().count('"batch ') == len(SHAPES) - 1
+    b2 = omt.BatchSolver(_problems(torch, 71, dtype=dt))
+    rows2, us2 = b2.autotune(0)
+    assert us2 == 0.0
+    assert rows2[:1] + rows2[2:] == rows[:1] + rows[2:]

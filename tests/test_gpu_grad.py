@@ -96,3 +96,17 @@ def test_batched_loss_falls_back_for_graphs_the_batch_does_not_compile():
     s = omt.Solver(a[1].detach(), b[1], I.path_edges(5))
     s.solve(200, 0.0, 64)
     assert torch.equal(s.grad()[0], a.grad[1])
+
+
+def test_loss_flags_unconverged_solves():
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    note("case: loss stopped above tol, 20x24 k3, 128 iterations")
+    r0, r1 = I.random_pair(72, 20, 24, 3)
+    a = to_dev(torch, r0, torch.float64)
+    b = to_dev(torch, r1, torch.float64)
+    with pytest.warns(omt.NotConvergedWarning):
+        omt.omt_loss(a, b, I.TRIANGLE, max_iters=128, tol=1e-9, tau=1.0)
+    with pytest.raises(omt.OMTError) as e:
+        omt.omt_loss(a[None], b[None], I.TRIANGLE, max_iters=128, tol=1e-9, tau=1.0, on_notconv="raise")
+    assert e.value.status == omt.ENOTCONV
