@@ -20,6 +20,7 @@ import json
 import os
 import sys
 import time
+import warnings
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -50,6 +51,10 @@ def _parse():
     ap.add_argument("--pairs", type=int, default=96, help="batched workload: number of pairs")
     ap.add_argument("--tol", type=float, default=0.0, help="time-to-tolerance workloads: tolerance (0: workload's)")
     ap.add_argument("--cap", type=int, default=3_000_000, help="time-to-tolerance workloads: iteration cap")
+    ap.add_argument("--batch-tune", action="store_true",
+                    help="batched workload: rows per strip from omt_batch_autotune instead of the default rule")
+    ap.add_argument("--floor-iters", type=int, default=0,
+                    help="loss workload: FP64 iterations before the FP32 floors are measured (0: skip)")
     ap.add_argument("--leg", default="both", choices=["both", "plain", "batched"],
                     help="batched workload: time both legs (ratio) or one of them")
     ap.add_argument("--plain-range", default="", metavar="A:B",
@@ -75,15 +80,19 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 5}), flush=True)
 
 
-def _kernel_hash():
+STEP_SOURCES = ("step.hip", "step_device.h", "omt_kernels.h")
+STEP3_SOURCES = ("step3.hip", "grid3.h", "step_device.h", "omt_kernels.h")
+
+
+def _kernel_hash(files=STEP_SOURCES):
     h = hashlib.sha256()
-    for f in ("step.hip", "step_device.h", "omt_kernels.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1712_10279_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(tblock, size, rows=0):
+def _traffic(key, rows=0, files=STEP_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source and the same launch shape."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -92,12 +101,74 @@ def _traffic(tblock, size, rows=0):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    e = t.get(f"T{tblock}_n{size}")
-    if not e or e.get("kernel_sha") != _kernel_hash():
+    e = t.get(key)
+    if not e or e.get("kernel_sha") != _kernel_hash(files):
         return None
     if rows and e.get("rows") not in (None, rows):
         return None
     return e.get("bytes_per_launch")
+
+
+def _timed_from_active_state(s, edges, alpha, tau, T, rows, launches, chunk_iters=32):
+    """Time the step kernel (HIP events on the solver's stream, omt_time_steps)
+    from a seeded synthetic state in which the flux and transfer shrinks are
+    active on most pixels (inputs.warm_state, scaled by the resolved mu and
+    nu), so that the measurement never sits in the regime where every shrink
+    returns zero.  The iteration relaxes the channel differences of such a
+    state within a few hundred iterations (w returns to zero where the data
+    need no transfer), so the state is loaded again before every
+    ``chunk_iters`` iterations of timed launches.  Returns (mean us per
+    launch, activity of the state after the last timed launch)."""
+    import torch
+    from paper_1712_10279_amd import inputs as I
+    from paper_1712_10279_amd import omt
+    m, n, p, k, l = s.m, s.n, s.p, s.k, s.l
+    _, mu, nu, _ = omt.resolve_params(m, n, k, edges, depth=p, alpha=alpha, tau=tau)
+    kw = dict(u_scale=mu, w_scale=50.0 * alpha * nu, offset=alpha)
+    phi, u, w = I.warm_state3(1, m, n, p, k, l, **kw) if p else I.warm_state(1, m, n, k, l, **kw)
+    dev = lambda x: torch.as_tensor(x, dtype=s.dtype, device=s.device)  # noqa: E731
+    phi, u, w = dev(phi), dev(u), dev(w) if l else None
+    per = max(1, chunk_iters // T)
+    times = []
+    for _ in range(max(1, launches // per)):
+        s.set_state(phi, u, w)
+        times.append(s.time_steps(T, rows, per))
+    return sum(times) / len(times), _activity(s)
+
+
+def _activity(s):
+    """Fractions of cells where the current u (any channel, any axis) and w
+    (any edge) are non-zero."""
+    st = s.get_state()
+    cells = s.m * s.n * max(s.p, 1)
+    u = float(((st["u"] != 0).reshape(cells, -1).any(dim=1)).double().mean())
+    w = float(((st["w"] != 0).reshape(cells, -1).any(dim=1)).double().mean()) if s.l else 0.0
+    return {"u_active": u, "w_active": w}
+
+
+def _fp32_floor(r0, r1, edges, alpha, tau, state64, V64, g64, iters=2048):
+    """What FP32 iterates give on a problem solved in FP64: plain and
+    compensated FP32 solves start from the FP64 iterate (rounded to FP32)
+    and run ``iters`` iterations; the largest relative residual of their
+    last four 512-iteration solves is the floor they sustain there (a
+    tolerance below it is out of reach in that precision), and V and Phi are
+    compared with the FP64 run's."""
+    import torch
+    from paper_1712_10279_amd import omt
+    out = {}
+    for comp in (False, True):
+        s = omt.Solver(r0.float(), r1.float(), edges, alpha=alpha, tau=tau, compensated=comp)
+        w = state64["w"].float() if state64["w"].shape[-1] else None
+        s.set_state(state64["phi"].float(), state64["u"].float(), w)
+        res = [s.solve(512, 0.0, 64)["residual"] for _ in range(max(4, iters // 512))]
+        V, _ = s.distance()
+        g, _ = s.grad()
+        out["compensated" if comp else "plain"] = {
+            "residual_floor": max(res[-4:]), "rel_V_vs_fp64": abs(V - V64) / V64 if V64 else abs(V),
+            "max_abs_Phi_vs_fp64": float((g.double() - g64).abs().max())}
+        del s
+    torch.cuda.synchronize()
+    return out
 
 
 def cpu_baseline(d, iters):
@@ -134,6 +205,20 @@ def _precision(a, default):
 def _dtype_name(dt):
     import torch
     return "f64" if dt == torch.float64 else "f32"
+
+
+def _floor_summary(floors, tol):
+    """Per precision: how many pairs sustain a residual below tol, the
+    largest floor, and the largest V and Phi errors against FP64."""
+    out = {}
+    for key in ("plain", "compensated"):
+        fl = [f[key] for f in floors]
+        out[key] = {"pairs_below_tol": sum(f["residual_floor"] <= tol for f in fl), "pairs": len(fl),
+                    "max_residual_floor": max(f["residual_floor"] for f in fl),
+                    "median_residual_floor": sorted(f["residual_floor"] for f in fl)[len(fl) // 2],
+                    "max_rel_V_vs_fp64": max(f["rel_V_vs_fp64"] for f in fl),
+                    "max_abs_Phi_vs_fp64": max(f["max_abs_Phi_vs_fp64"] for f in fl)}
+    return out
 
 
 def bench_batched(a):
@@ -177,6 +262,12 @@ def bench_batched(a):
     if a.leg in ("both", "batched"):
         os.environ["OMT_VERBOSE"] = "1"
         b = omt.BatchSolver(probs)
+        tuned_rows = None
+        if a.batch_tune:
+            # untimed: rows per strip for every shape class (iterates unchanged)
+            tuned_rows, tuned_us = b.autotune()
+            print(f"# batched: tuned rows {sorted(set(tuned_rows))}, {tuned_us:.1f} us per all-active iteration",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         batch = b.solve(a.cap, tol, 64)
@@ -184,6 +275,16 @@ def bench_batched(a):
         t_batch = time.perf_counter() - t0
         print(f"# batched: {t_batch:.1f} s", file=sys.stderr, flush=True)
     ref = batch if batch is not None else plain
+    floors = None
+    if batch is not None and dt == torch.float64:
+        # FP32 floors of every pair at its FP64 solution
+        Vb = b.distance()
+        gb, _ = b.grad()
+        floors = []
+        for q, p in enumerate(probs):
+            fl = _fp32_floor(p["rho0"], p["rho1"], p["edges"], p["alpha"], p["tau"], b.get_state(q), Vb[q], gb[q])
+            floors.append({"pair": q, "side": specs[q]["side"], "k": specs[q]["k"], **fl})
+        print(f"# batched: FP32 floors measured", file=sys.stderr, flush=True)
     its = [i["iters"] for i in ref]
     if batch is None and a.plain_range:
         specs = specs[lo:hi]
@@ -194,7 +295,10 @@ def bench_batched(a):
     if plain is not None:
         extra.update(plain_s=t_plain, plain_cell_iter_per_s=cells / t_plain)
     if batch is not None:
-        extra.update(batched_s=t_batch, batched_cell_iter_per_s=cells / t_batch)
+        extra.update(batched_s=t_batch, batched_cell_iter_per_s=cells / t_batch, batched_rows=tuned_rows)
+    if floors is not None:
+        extra["fp32"] = _floor_summary(floors, tol)
+        extra["fp32_per_pair"] = floors
     if plain is not None and batch is not None:
         extra["same_iterations"] = all(p["iters"] == q["iters"] for p, q in zip(plain, batch))
         value, unit, metric = t_plain / t_batch, "x", "time to 1e-5 relative residual, batched vs plain"
@@ -222,9 +326,9 @@ def bench_rgb(a):
     total_t, total_it = 0.0, 0
     for alpha in (0.5, 1.0, 4.0):
         d = I.rgb_256(alpha)
-        s = omt.Solver(torch.as_tensor(d["rho0"], dtype=dt, device="cuda"),
-                       torch.as_tensor(d["rho1"], dtype=dt, device="cuda"), d["edges"], alpha=alpha,
-                       tau=I.tuned_tau(256, 256), compensated=comp)
+        s_r0 = torch.as_tensor(d["rho0"], dtype=dt, device="cuda")
+        s_r1 = torch.as_tensor(d["rho1"], dtype=dt, device="cuda")
+        s = omt.Solver(s_r0, s_r1, d["edges"], alpha=alpha, tau=I.tuned_tau(256, 256), compensated=comp)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = s.solve(a.cap, tol, 64)
@@ -233,8 +337,15 @@ def bench_rgb(a):
         total_t += el
         total_it += info["iters"]
         print(f"# rgb alpha {alpha}: {info['iters']} it, {el:.2f} s", file=sys.stderr, flush=True)
-        out.append({"alpha": alpha, "seconds": el, "iterations": info["iters"], "converged": info["converged"],
-                    "V": s.distance()[0], "rel_gap": info["rel_gap"]})
+        V = s.distance()[0]
+        row = {"alpha": alpha, "seconds": el, "iterations": info["iters"], "converged": info["converged"],
+               "residual": info["residual"], "V": V, "rel_gap": info["rel_gap"]}
+        if dt == torch.float64:
+            row["fp32"] = _fp32_floor(s_r0, s_r1, d["edges"], alpha, I.tuned_tau(256, 256), s.get_state(), V,
+                                      s.grad()[0])
+            print(f"# rgb alpha {alpha}: FP32 floors plain {row['fp32']['plain']['residual_floor']:.2e} "
+                  f"compensated {row['fp32']['compensated']['residual_floor']:.2e}", file=sys.stderr, flush=True)
+        out.append(row)
     return _line("time to 1e-5 relative residual", total_t, "s", total_it, 0, total_t * 1e3 / total_it,
                  dtype=_dtype_name(dt), config={"workload": "vomt_256x256_k3_triangle_3alphas", "tol": tol,
                                                 "precision": label, "tau": I.tuned_tau(256, 256),
@@ -253,13 +364,38 @@ def bench_loss(a):
     r1 = torch.stack([torch.as_tensor(d["rho1"], dtype=dt, device="cuda") for d in ds])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    V = omt.omt_loss(r0, r1, I.TRIANGLE, max_iters=a.cap, tol=tol, tau=I.tuned_tau(512, 512), compensated=comp)
-    V.sum().backward()
+    tau = a.tau or ds[0]["tau"]
+    with warnings.catch_warnings(record=True) as caught:
+        warnings.simplefilter("always")
+        V = omt.omt_loss(r0, r1, I.TRIANGLE, max_iters=a.cap, tol=tol, tau=tau, compensated=comp)
+        V.sum().backward()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    notconv = [str(w.message) for w in caught if issubclass(w.category, omt.NotConvergedWarning)]
+    extra = {}
+    if dt == torch.float64 and a.floor_iters > 0:
+        # untimed: the same pairs solved by the batched FP64 solver for
+        # floor_iters iterations (or to tol), then the FP32 floors at that
+        # iterate, pair by pair
+        b = omt.BatchSolver([dict(rho0=r0[q].detach(), rho1=r1[q], edges=I.TRIANGLE, tau=tau) for q in range(len(ds))])
+        infos = b.solve(a.floor_iters, tol, 64)
+        Vb = b.distance()
+        gb, _ = b.grad()
+        rows = []
+        for q, info in enumerate(infos):
+            rows.append({"pair": q, "iterations": info["iters"], "converged": info["converged"],
+                         "residual": info["residual"],
+                         **_fp32_floor(r0[q].detach(), r1[q], I.TRIANGLE, 1.0, tau, b.get_state(q), Vb[q], gb[q])})
+            print(f"# loss pair {q}: {info['iters']} it, residual {info['residual']:.2e}, FP32 floors "
+                  f"{rows[-1]['plain']['residual_floor']:.2e} / {rows[-1]['compensated']['residual_floor']:.2e}",
+                  file=sys.stderr, flush=True)
+        del b
+        extra = {"fp32": _floor_summary(rows, tol), "fp32_floor_iterate": f"FP64 after up to {a.floor_iters} iterations",
+                 "per_pair": rows}
     return _line("forward+backward time, 8 pairs to 1e-6", el, "s", 8, 0, el * 1e3 / 8, dtype=_dtype_name(dt),
-                 config={"workload": "loss_8x512x512_k3_triangle", "tol": tol, "precision": label,
-                         "parallelism": "single-gpu"}, V=[float(v) for v in V.detach().cpu()])
+                 config={"workload": "loss_8x512x512_k3_triangle", "tol": tol, "tau": tau, "cap": a.cap,
+                         "precision": label, "parallelism": "single-gpu"}, V=[float(v) for v in V.detach().cpu()],
+                 not_converged=notconv, **extra)
 
 
 def bench_matrix(a):
@@ -348,21 +484,23 @@ def bench_volume(a):
     dt = time.perf_counter() - t0
     cells = m * n * p
     value = cells * iters * a.steps / dt
-    st = s.get_state()
-    u_act = float(((st["u"] != 0).reshape(cells, -1).any(dim=1)).double().mean())
-    w_act = float(((st["w"] != 0).reshape(cells, -1).any(dim=1)).double().mean())
-    us = s.time_steps(1, rows, max(1, a.timing_launches))
+    act = _activity(s)
+    us, timed_act = _timed_from_active_state(s, d["edges"], d["alpha"], d["tau"], 1, rows,
+                                             max(1, a.timing_launches))
     alg = (9 * k + 2 * l) * 4 * cells  # reads phi k, u 3k, w l, f k; writes phi k, u 3k, w l
     ach = alg / (us * 1e-6) / 1e9
+    traffic = _traffic(f"step3_{m}x{n}x{p}_k{k}", rows, STEP3_SOURCES)
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": None, "kernel": "pdhg_step3_kernel (one iteration per launch)", "us_per_launch": us,
-            "bytes_per_launch": alg}
+            "traffic": traffic, "kernel": "pdhg_step3_kernel (one iteration per launch)", "us_per_launch": us,
+            "bytes_per_launch": alg, "timed_from": "seeded active state (inputs.warm_state3)", **timed_act}
+    if traffic:
+        roof["counted_gbs"] = traffic / (us * 1e-6) / 1e9
+        roof["counted_frac"] = roof["counted_gbs"] / HBM_PEAK_GBS
     line = _line("PDHG cell-iterations/s, 3-D grid", value, "cell-iter/s", a.steps, a.warmup, dt * 1e3 / a.steps,
                  config={"workload": d["name"], "grid": [m, n, p], "channels": k, "edges": l, "graph": "triangle",
                          "alpha": d["alpha"], "tau": d["tau"], "iterations_per_step": iters, "check_every": 64,
                          "slices_per_wave": rows, "parallelism": "single-gpu"},
-                 roofline=roof, solve={"primal": V, "residual": info["residual"], "rel_gap": info["rel_gap"],
-                                       "u_active": u_act, "w_active": w_act})
+                 roofline=roof, solve={"primal": V, "residual": info["residual"], "rel_gap": info["rel_gap"], **act})
     if not a.no_cpu:
         import oracle.grid3 as G3
         q = G3.Problem3(m, n, p, k, edges=d["edges"], alpha=d["alpha"], tau=d["tau"])
@@ -439,21 +577,19 @@ def main():
     value = cells * iters * a.steps / dt
 
     # activity of the final iterate: where the shrinks returned non-zero
-    st = s.get_state()
-    u_act = float(((st["u"] != 0).reshape(m, n, -1).any(dim=2)).double().mean())
-    w_act = float(((st["w"] != 0).reshape(m, n, -1).any(dim=2)).double().mean()) if l else 0.0
+    act = _activity(s)
 
     # dominant kernel: the fused step, timed with HIP events on its own
-    # stream, from the solved (active) state
+    # stream, from a seeded state with u and w active
     launches = max(1, a.timing_launches // T) * T
-    us = s.time_steps(T, rows, launches)
+    us, timed_act = _timed_from_active_state(s, d["edges"], d["alpha"], d["tau"], T, rows, launches)
     alg_bytes = (7 * k + 2 * l) * 4 * cells * T
     achieved = alg_bytes / (us * 1e-6) / 1e9
-    traffic = _traffic(T, a.size, rows)
+    traffic = _traffic(f"T{T}_n{a.size}", rows)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": f"pdhg_step_kernel (T = {T} iterations per launch)", "us_per_launch": us,
-            "bytes_per_launch": alg_bytes}
+            "bytes_per_launch": alg_bytes, "timed_from": "seeded active state (inputs.warm_state)", **timed_act}
     if traffic:
         # what the memory system moved (counted bytes) at the same launch time
         roof["counted_gbs"] = traffic / (us * 1e-6) / 1e9
@@ -491,7 +627,7 @@ def main():
         "roofline": roof,
         "pixel_channel_iter_per_s": value * k,
         "solve": {"primal": V, "residual": info["residual"], "rel_gap": info["rel_gap"],
-                  "mass_residual": info["mass_residual"], "u_active": u_act, "w_active": w_act},
+                  "mass_residual": info["mass_residual"], **act},
         "fp32_vs_fp64": fp64,
     }
     if not a.no_cpu:

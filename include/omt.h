@@ -34,6 +34,14 @@
  *   - Exported potential: Phi = -phi with its mean over each mass class
  *     removed.  By the dual problem of Sec. 3.2, V = <phi, rho1 - rho0> at
  *     optimum, so dV/drho0 = Phi and dV/drho1 = -Phi.
+ *   - Diagnostics (environment, read once per process): OMT_LOG=1 prints
+ *     every failure to stderr, 2 also one line per solve (iterations, time,
+ *     residual) and the batch's progress, 3 also one line per check;
+ *     OMT_VERBOSE alone means 2.  Solves, check intervals and the other
+ *     entry points are ROCTx ranges (rocprofv3 --marker-trace).
+ *     OMT_POISON=1 fills the padding of every field (the columns past n of
+ *     each row and the gaps between planes) with NaN at create, so that a
+ *     kernel that read memory outside the grid would turn its results NaN.
  */
 #ifndef OMT_H
 #define OMT_H
@@ -206,7 +214,7 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
  * check_every iterations, as omt_solve); infos: host array of B (nullable).
  * Every call starts all B problems from their current iterates.  Environment:
  * OMT_BATCH_PERSISTENT selects the single persistent launch with grid
- * barriers instead of graph-replayed per-iteration launches; OMT_VERBOSE
+ * barriers instead of graph-replayed per-iteration launches; OMT_LOG >= 2
  * prints a line to stderr whenever more problems have stopped. */
 omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, int32_t check_every,
                            omt_info *infos);

@@ -70,7 +70,7 @@ def build(verbose: bool = False, jobs: int | None = None, defines=(), out: str |
             print(f"[{os.path.basename(obj)}] {warn}", flush=True)
     objs = [r[0] for r in results]
     lib = out or LIB
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", lib + ".tmp"] + objs
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", lib + ".tmp"] + objs + ["-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

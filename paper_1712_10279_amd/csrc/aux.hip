@@ -292,6 +292,19 @@ __global__ void zero_kernel(uint32_t *p, int64_t n)
         p[q] = 0u;
 }
 
+// Every 32-bit word of nplanes planes (stride_words apart) that lies outside
+// the grid -- past rows * row_words in the plane, or at a word column >=
+// n_words of a row -- becomes all ones, a NaN in FP32 and FP64 alike.
+__global__ void poison_kernel(uint32_t *p, int64_t nplanes, int64_t stride_words, int64_t row_words, int64_t rows,
+                              int64_t n_words)
+{
+    const int64_t total = nplanes * stride_words;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = q % stride_words;
+        if (o / row_words >= rows || o % row_words >= n_words) p[q] = 0xFFFFFFFFu;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_sums(const SumsArgs &a, hipStream_t s)
@@ -346,6 +359,18 @@ hipError_t launch_matrix_xfer(const MatrixXferArgs &a, hipStream_t s)
     const int64_t n = a.npix * a.count;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(matrix_xfer_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_poison(void *p, int64_t nplanes, size_t plane_stride_bytes, int row_elems, int64_t rows, int n,
+                         int esz, hipStream_t s)
+{
+    if (nplanes <= 0 || plane_stride_bytes % 4 != 0 || esz % 4 != 0) return nplanes <= 0 ? hipSuccess : hipErrorInvalidValue;
+    const int64_t stride_words = int64_t(plane_stride_bytes / 4), total = nplanes * stride_words;
+    const int64_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(poison_kernel, dim3(unsigned(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s,
+                       static_cast<uint32_t *>(p), nplanes, stride_words, int64_t(row_elems) * (esz / 4), rows,
+                       int64_t(n) * (esz / 4));
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 // workspace layout, the iteration loop with its check cadence, and the
 // stopping rule on the fixed-point residual R^k of Sec. 6.1.
 
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -142,6 +143,18 @@ namespace {
 // to report an error)
 thread_local char g_last_error[512];
 
+// Verbosity from OMT_LOG (read once): 0 silent, 1 every failure, 2 also a
+// line per solve, 3 also a line per check.  OMT_VERBOSE alone means 2.
+int log_level()
+{
+    static const int level = [] {
+        const char *v = std::getenv("OMT_LOG");
+        if (v && *v) return std::max(0, std::atoi(v));
+        return std::getenv("OMT_VERBOSE") ? 2 : 0;
+    }();
+    return level;
+}
+
 omt_status fail(omt_status s, const char *fmt, ...)
 {
     char buf[512];
@@ -150,8 +163,18 @@ omt_status fail(omt_status s, const char *fmt, ...)
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
     std::memcpy(g_last_error, buf, sizeof(buf));
+    if (log_level() >= 1) std::fprintf(stderr, "omt: %s: %s\n", s == OMT_OK ? "note" : omt_strerror(s), buf);
     return s;
 }
+
+// A named range on the ROCTx marker stream (visible to rocprofv3
+// --marker-trace; a no-op without a tool attached) for the scope's lifetime.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 #define HIP_TRY(expr)                                                                               \
     do {                                                                                            \
@@ -1008,7 +1031,10 @@ omt_status solve_ctx(omt_ctx *h, int64_t max_iters, double tol, int32_t check_ev
     const int rowsT = default_rows(h, T), rows1 = default_rows(h, 1);
     const bool use_graph = allow_graph && K >= 8;
     if (use_graph) HIP_TRY(hipStreamSynchronize(h->stream));
+    const int verbosity = log_level();
+    const auto t_start = std::chrono::steady_clock::now();
     while (it < max_iters) {
+        TraceRange range("omt check interval");
         const int64_t nblk = std::min<int64_t>(K, max_iters - it);
         if (use_graph && nblk == K) {
             if ((s = graph_interval(h, K, T, rowsT, rows1)) != OMT_OK) return s;
@@ -1020,6 +1046,9 @@ omt_status solve_ctx(omt_ctx *h, int64_t max_iters, double tol, int32_t check_ev
         fill_info(h, h->host, &inf);
         inf.iters = it;
         inf.checks += 1;
+        if (verbosity >= 3)
+            std::fprintf(stderr, "omt: %lld iterations: residual %.3e, primal %.9g, dual %.9g, gap %.2e\n",
+                         (long long)it, inf.residual, inf.primal, inf.dual, inf.rel_gap);
         if (!std::isfinite(inf.R) || !std::isfinite(inf.primal)) {
             h->last = inf;
             h->have_last = true;
@@ -1035,6 +1064,13 @@ omt_status solve_ctx(omt_ctx *h, int64_t max_iters, double tol, int32_t check_ev
     h->last = inf;
     h->have_last = true;
     if (info) *info = inf;
+    if (verbosity >= 2) {
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        std::fprintf(stderr, "omt: solve of %dx%dx%d k %d: %lld iterations in %.3f ms (T %d, %d rows), residual %.3e%s\n",
+                     h->r.m, h->r.n, h->r.p, h->r.k, (long long)it, ms, T, rowsT, inf.residual,
+                     inf.converged ? ", converged" : "");
+    }
     if (tol > 0.0 && !inf.converged) return fail(OMT_ENOTCONV, "residual %.3g > tol %.3g after %lld iterations",
                                                   inf.residual, tol, (long long)it);
     return OMT_OK;
@@ -1126,6 +1162,7 @@ omt_status omt_workspace_bytes(const omt_params *p, size_t *bytes)
 omt_status omt_create(const omt_params *p, const void *rho0, const void *rho1, void *workspace, size_t ws_bytes,
                       void *stream, omt_handle *out)
 {
+    TraceRange range("omt_create");
     if (!out) return fail(OMT_EINVAL, "out is NULL");
     *out = nullptr;
     Resolved r;
@@ -1248,6 +1285,16 @@ omt_status setup_ctx(omt_ctx *h, const Resolved &r, const void *rho0, const void
     fa.f = h->f;
     if (e == hipSuccess) e = launch_zero(h->ws, L.off_part, h->stream);
     if (e == hipSuccess) e = launch_make_f(fa, h->stream);
+    if (e == hipSuccess && std::getenv("OMT_POISON")) {
+        // padding of f, phi, u, w (one plane stride apart), then of the
+        // compensated low parts (FP32 planes)
+        const size_t pb = align256(size_t(L.plane) * L.esz), pf = align256(size_t(L.plane) * 4);
+        const int64_t rows = int64_t(r.m) * r.p;
+        const int64_t nfield = int64_t(r.k) * 3 + int64_t(ucomp(r)) * r.k * 2 + int64_t(r.l) * 2;
+        e = launch_poison(h->ws + L.off_f, nfield, pb, L.pitch, rows, r.n, int(L.esz), h->stream);
+        if (e == hipSuccess && r.comp)
+            e = launch_poison(h->ws + L.off_plo[0], int64_t(r.k) * 2, pf, L.pitch, rows, r.n, 4, h->stream);
+    }
     if (e != hipSuccess) return fail(OMT_EDEVICE, "set-up: %s", hipGetErrorString(e));
     // ||f||^2 from the objectives of the zero state
     s = run_metrics(h, 0, 0, 0, 0);
@@ -1263,6 +1310,7 @@ extern "C" {
 
 omt_status omt_solve(omt_handle h, int64_t max_iters, double tol, int32_t check_every, omt_info *info)
 {
+    TraceRange range("omt_solve");
     if (!h) return fail(OMT_EINVAL, "handle is NULL");
     // full intervals are replayed as graphs unless OMT_NO_GRAPH is set
     return solve_ctx(h, max_iters, tol, check_every, info, !std::getenv("OMT_NO_GRAPH"));
@@ -1270,6 +1318,7 @@ omt_status omt_solve(omt_handle h, int64_t max_iters, double tol, int32_t check_
 
 omt_status omt_distance(omt_handle h, double *V, omt_info *info)
 {
+    TraceRange range("omt_distance");
     if (!h) return fail(OMT_EINVAL, "handle is NULL");
     omt_status s = run_metrics(h, h->cur, h->cur, h->wcur, h->wcur);
     if (s == OMT_OK) s = read_results(h, NMET);
@@ -1291,6 +1340,7 @@ omt_status omt_distance(omt_handle h, double *V, omt_info *info)
 
 omt_status omt_grad(omt_handle h, void *d_rho0, void *d_rho1)
 {
+    TraceRange range("omt_grad");
     if (!h) return fail(OMT_EINVAL, "handle is NULL");
     const Resolved &r = h->r;
     PlaneSumArgs pa;
@@ -1465,6 +1515,7 @@ omt_status omt_time_steps(omt_handle h, int32_t T, int32_t rows_per_wave, int64_
 omt_status omt_solve_static(const omt_params *p, const void *rho0, const void *rho1, int64_t max_iters, double tol,
                             int32_t check_every, double *V, void *d_rho0, void *d_rho1, omt_info *info, void *stream)
 {
+    TraceRange range("omt_solve_static");
     Resolved r;
     omt_status s = resolve(p, r);
     if (s != OMT_OK) return s;
@@ -1491,6 +1542,7 @@ omt_status omt_solve_static(const omt_params *p, const void *rho0, const void *r
 
 omt_status omt_autotune(omt_handle h, int32_t iters_per_trial, int32_t *best_t, int32_t *best_rows, double *best_us)
 {
+    TraceRange range("omt_autotune");
     if (!h) return fail(OMT_EINVAL, "handle is NULL");
     const Resolved &r = h->r;
     const size_t pb = align256(size_t(h->L.plane) * h->L.esz), pf = align256(size_t(h->L.plane) * 4);
@@ -1789,7 +1841,7 @@ omt_status batch_solve_graphs(omt_bctx *h, BatchArgs ba, int64_t max_iters, int 
     int64_t done = 0;
     int nchecks = 0;
     unsigned stopped = 0;
-    const bool verbose = std::getenv("OMT_VERBOSE") != nullptr;
+    const bool verbose = log_level() >= 2;
     auto last_note = std::chrono::steady_clock::now();
     while (done < max_iters && stopped < unsigned(h->B)) {
         const int64_t nblk = std::min<int64_t>(K, max_iters - done);
@@ -1990,6 +2042,7 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
 
 omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, int32_t check_every, omt_info *infos)
 {
+    TraceRange range("omt_batch_solve");
     if (!h) return fail(OMT_EINVAL, "handle is NULL");
     if (max_iters < 0) return fail(OMT_EINVAL, "max_iters < 0");
     const int K = check_every > 0 ? check_every : 64;
@@ -2105,6 +2158,7 @@ omt_status omt_batch_set_state(omt_batch_handle h, int32_t b, const void *phi, c
 
 omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, int32_t *rows, double *us_per_iter)
 {
+    TraceRange range("omt_batch_autotune");
     if (!h) return fail(OMT_EINVAL, "handle is NULL");
     if (launches_per_trial < 0) return fail(OMT_EINVAL, "launches_per_trial < 0");
     if (launches_per_trial == 0) {

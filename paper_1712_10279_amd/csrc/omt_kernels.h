@@ -231,6 +231,11 @@ struct XferArgs {
 hipError_t launch_xfer(const XferArgs &a, hipStream_t s);
 
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// NaN (all-ones words) into the padding of nplanes planes of plane_stride_bytes
+// each: rows of row_elems elements of esz bytes, of which the first n are
+// the grid's; everything past rows * row_elems in a plane is padding too
+hipError_t launch_poison(void *p, int64_t nplanes, size_t plane_stride_bytes, int row_elems, int64_t rows, int n,
+                         int esz, hipStream_t s);
 
 // Matrices <-> orthonormal real coordinates of the matrix method.  Per pixel
 // `count` k x k matrices (complex (re, im) pairs, or real entries when real

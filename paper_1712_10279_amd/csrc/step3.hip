@@ -96,53 +96,58 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(con
     // potential of the current slice and of the next, rows i0 - 1 .. i0 + RT
     R pc[RT + 2][K], pn[RT + 2][K];
     R carry[RT][K];  // 2 u_z' - u_z of the previous slice, tile rows
+    // fluxes (rows i0 - 1 .. i0 + RT - 1), transfers and source (tile rows)
+    // of the current slice
+    R ux[RT + 1][K], uy[RT + 1][K], uz[RT + 1][K];
+    R wv[RT][LA], fv[RT][K];
 #pragma unroll
     for (int q = 0; q < RT; ++q)
 #pragma unroll
         for (int c = 0; c < K; ++c) carry[q][c] = R(0);
+    // loads of one row of a slice; ok = false gives a zero-length
+    // descriptor (zeros, no memory access)
+    auto ld_phi = [&](R (&dst)[K], int z, int i, bool ok) {
+        const auto rp = row_rsrc(a.phi_in, roff(z, i), ok && row_ok(i) && z < a.p, nb_phi);
 #pragma unroll
-    for (int q = 0; q < RT + 2; ++q) {
+        for (int c = 0; c < K; ++c) dst[c] = buf_ld<R>(rp, voff + unsigned(c) * Psz);
+    };
+    auto ld_u = [&](int q, int z, bool ok) {
         const int i = i0 - 1 + q;
-        const auto rp = row_rsrc(a.phi_in, roff(zs, i), row_ok(i), nb_phi);
+        const auto ru = row_rsrc(a.u_in, roff(z, i), ok && row_ok(i), nb_u);
 #pragma unroll
-        for (int c = 0; c < K; ++c) pc[q][c] = buf_ld<R>(rp, voff + unsigned(c) * Psz);
-    }
+        for (int c = 0; c < K; ++c) {
+            ux[q][c] = buf_ld<R>(ru, voff + unsigned(c) * Psz);
+            uy[q][c] = buf_ld<R>(ru, voff + unsigned(K + c) * Psz);
+            uz[q][c] = buf_ld<R>(ru, voff + unsigned(2 * K + c) * Psz);
+        }
+    };
+    auto ld_wf = [&](int r, int z, bool ok) {
+        const int i = i0 + r;
+        ok = ok && row_ok(i);
+        const auto rw = row_rsrc(a.w_in, roff(z, i), ok && L > 0, nb_w);
+        const auto rf = row_rsrc(a.f, roff(z, i), ok, nb_phi);
+#pragma unroll
+        for (int e = 0; e < LA; ++e) wv[r][e] = L > 0 ? buf_ld<R>(rw, soff + unsigned(e) * Psz) : R(0);
+#pragma unroll
+        for (int c = 0; c < K; ++c) fv[r][c] = buf_ld<R>(rf, voff + unsigned(c) * Psz);
+    };
+    // the first slice: its potential, the next slice's, its fluxes, and
+    // (if the wave stores it) its transfers and source
+#pragma unroll
+    for (int q = 0; q < RT + 2; ++q) ld_phi(pc[q], zs, i0 - 1 + q, true);
+#pragma unroll
+    for (int q = 0; q < RT + 2; ++q) ld_phi(pn[q], zs + 1, i0 - 1 + q, true);
+#pragma unroll
+    for (int q = 0; q < RT + 1; ++q) ld_u(q, zs, true);
+#pragma unroll
+    for (int r = 0; r < RT; ++r) ld_wf(r, zs, zs >= z0);
 
     for (int z = zs; z < z1; ++z) {
         const bool inner = z >= z0;  // a slice this wave stores (else the halo slice)
         const bool zlast = z == a.p - 1;
-#pragma unroll
-        for (int q = 0; q < RT + 2; ++q) {
-            const int i = i0 - 1 + q;
-            const auto rp = row_rsrc(a.phi_in, roff(z + 1, i), row_ok(i) && z + 1 < a.p, nb_phi);
-#pragma unroll
-            for (int c = 0; c < K; ++c) pn[q][c] = buf_ld<R>(rp, voff + unsigned(c) * Psz);
-        }
-        R ux[RT + 1][K], uy[RT + 1][K], uz[RT + 1][K];
-#pragma unroll
-        for (int q = 0; q < RT + 1; ++q) {
-            const int i = i0 - 1 + q;
-            const auto ru = row_rsrc(a.u_in, roff(z, i), row_ok(i), nb_u);
-#pragma unroll
-            for (int c = 0; c < K; ++c) {
-                ux[q][c] = buf_ld<R>(ru, voff + unsigned(c) * Psz);
-                uy[q][c] = buf_ld<R>(ru, voff + unsigned(K + c) * Psz);
-                uz[q][c] = buf_ld<R>(ru, voff + unsigned(2 * K + c) * Psz);
-            }
-        }
-        R wv[RT][LA], fv[RT][K];
-#pragma unroll
-        for (int q = 0; q < RT; ++q) {
-            const int i = i0 + q;
-            const bool ok = row_ok(i) && inner;
-            const auto rw = row_rsrc(a.w_in, roff(z, i), ok && L > 0, nb_w);
-            const auto rf = row_rsrc(a.f, roff(z, i), ok, nb_phi);
-#pragma unroll
-            for (int e = 0; e < LA; ++e) wv[q][e] = L > 0 ? buf_ld<R>(rw, soff + unsigned(e) * Psz) : R(0);
-#pragma unroll
-            for (int c = 0; c < K; ++c) fv[q][c] = buf_ld<R>(rf, voff + unsigned(c) * Psz);
-        }
-
+        // the next slice is loaded row by row as this one frees its
+        // registers, so its loads are in flight while this slice computes
+        const bool more = z + 1 < z1;
         R ubxp[K];  // 2 u_x' - u_x of the row above
 #pragma unroll
         for (int c = 0; c < K; ++c) ubxp[c] = R(0);
@@ -233,11 +238,17 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(con
             }
 #pragma unroll
             for (int c = 0; c < K; ++c) ubxp[c] = ubx[c];
-        }
-#pragma unroll
-        for (int q = 0; q < RT + 2; ++q)
+            // row q of this slice is done with its flux, potential and
+            // (row q - 1) transfer and source: load the next slice's
+            ld_u(q, z + 1, more);
+            if (q >= 1) ld_wf(q - 1, z + 1, more);
 #pragma unroll
             for (int c = 0; c < K; ++c) pc[q][c] = pn[q][c];
+            ld_phi(pn[q], z + 2, i0 - 1 + q, more);
+        }
+#pragma unroll
+        for (int c = 0; c < K; ++c) pc[RT + 1][c] = pn[RT + 1][c];
+        ld_phi(pn[RT + 1], z + 2, i0 + RT, more);
     }
 }
 

@@ -23,15 +23,18 @@ def test_traffic_only_for_the_profiled_source_and_shape():
         entries = json.load(fh)
     assert entries, "no counter summary committed"
     for key, e in entries.items():
-        T, size = int(key.split("_")[0][1:]), int(key.split("_n")[1])
+        files = tuple(e["sources"])
+        assert files in (bench.STEP_SOURCES, bench.STEP3_SOURCES)
+        rows = e.get("rows", 0)
         # reported for the source the counters were taken on, else null
-        if e["kernel_sha"] != bench._kernel_hash():
-            assert bench._traffic(T, size, e.get("rows", 0)) is None
+        if e["kernel_sha"] != bench._kernel_hash(files):
+            assert bench._traffic(key, rows, files) is None
             continue
-        assert bench._traffic(T, size, e.get("rows", 0)) == e["bytes_per_launch"]
-        # other shapes and sizes have no counters
-        assert bench._traffic(T, size, (e.get("rows") or 1) + 1) is None
-        assert bench._traffic(T + 8, size) is None
-        assert bench._traffic(T, size + 1) is None
-        # counted traffic is positive and no more than the algorithmic bytes of T one-pass iterations
-        assert 0 < e["bytes_per_launch"] <= (7 * 8 + 2 * 7) * 4 * size * size * T * 1.5
+        assert bench._traffic(key, rows, files) == e["bytes_per_launch"]
+        # other shapes, sizes and kernels have no counters
+        assert bench._traffic(key, (rows or 1) + 1, files) is None
+        assert bench._traffic(key + "_other", rows, files) is None
+        other = bench.STEP3_SOURCES if files == bench.STEP_SOURCES else bench.STEP_SOURCES
+        assert bench._traffic(key, rows, other) is None
+        # counted traffic is positive and within 1.5x of the launch's algorithmic bytes
+        assert 0 < e["bytes_per_launch"] <= 1.5 * e["algorithmic_bytes"]
