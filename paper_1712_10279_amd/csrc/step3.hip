@@ -313,29 +313,42 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void tile_metrics3_kernel(
         double acc[NMET];
 #pragma unroll
         for (int q = 0; q < NMET; ++q) acc[q] = 0.0;
+        // every load is issued unconditionally (the addresses are clamped
+        // into the field), so they all can be in flight at once; ghost and
+        // outside neighbours are zeroed afterwards
         double we0[LA], we1[LA];
 #pragma unroll
         for (int e = 0; e < LA; ++e) {
-            const bool on = L > 0 && e < a.l;
-            we0[e] = on ? double(ld_field(&w0[e * P + o])) : 0.0;
-            we1[e] = on ? double(ld_field(&w1[e * P + o])) : 0.0;
+            we0[e] = we1[e] = 0.0;
+            if constexpr (L > 0) {
+                // a type compiled for more edges than in use reads plane 0
+                // again for the missing ones and drops it
+                const bool on = e < a.l;
+                const int64_t oe = on ? e * P + o : o;
+                const double v0 = double(ld_field(&w0[oe])), v1 = double(ld_field(&w1[oe]));
+                we0[e] = on ? v0 : 0.0;
+                we1[e] = on ? v1 : 0.0;
+            }
         }
         double u2 = 0.0, sq = 0.0;
 #pragma unroll
         for (int c = 0; c < K; ++c) {
             const double p0 = double(ld_field(&phi0[c * P + o])), p1 = double(ld_field(&phi1[c * P + o]));
-            const double ux0 = i < a.m - 1 ? double(ld_field(&u0[c * P + o])) : 0.0;
-            const double ux1 = i < a.m - 1 ? double(ld_field(&u1[c * P + o])) : 0.0;
-            const double uy0 = j < a.n - 1 ? double(ld_field(&u0[(K + c) * P + o])) : 0.0;
-            const double uy1 = j < a.n - 1 ? double(ld_field(&u1[(K + c) * P + o])) : 0.0;
-            const double uz0 = z < a.p - 1 ? double(ld_field(&u0[(2 * K + c) * P + o])) : 0.0;
-            const double uz1 = z < a.p - 1 ? double(ld_field(&u1[(2 * K + c) * P + o])) : 0.0;
-            const double xl0 = i > 0 ? double(ld_field(&u0[c * P + oi])) : 0.0;
-            const double xl1 = i > 0 ? double(ld_field(&u1[c * P + oi])) : 0.0;
-            const double yl0 = j > 0 ? double(ld_field(&u0[(K + c) * P + oj])) : 0.0;
-            const double yl1 = j > 0 ? double(ld_field(&u1[(K + c) * P + oj])) : 0.0;
-            const double zl0 = z > 0 ? double(ld_field(&u0[(2 * K + c) * P + oz])) : 0.0;
-            const double zl1 = z > 0 ? double(ld_field(&u1[(2 * K + c) * P + oz])) : 0.0;
+            const double lx0 = double(ld_field(&u0[c * P + o])), lx1 = double(ld_field(&u1[c * P + o]));
+            const double ly0 = double(ld_field(&u0[(K + c) * P + o])), ly1 = double(ld_field(&u1[(K + c) * P + o]));
+            const double lz0 = double(ld_field(&u0[(2 * K + c) * P + o]));
+            const double lz1 = double(ld_field(&u1[(2 * K + c) * P + o]));
+            const double lxl0 = double(ld_field(&u0[c * P + oi])), lxl1 = double(ld_field(&u1[c * P + oi]));
+            const double lyl0 = double(ld_field(&u0[(K + c) * P + oj]));
+            const double lyl1 = double(ld_field(&u1[(K + c) * P + oj]));
+            const double lzl0 = double(ld_field(&u0[(2 * K + c) * P + oz]));
+            const double lzl1 = double(ld_field(&u1[(2 * K + c) * P + oz]));
+            const double ux0 = i < a.m - 1 ? lx0 : 0.0, ux1 = i < a.m - 1 ? lx1 : 0.0;
+            const double uy0 = j < a.n - 1 ? ly0 : 0.0, uy1 = j < a.n - 1 ? ly1 : 0.0;
+            const double uz0 = z < a.p - 1 ? lz0 : 0.0, uz1 = z < a.p - 1 ? lz1 : 0.0;
+            const double xl0 = i > 0 ? lxl0 : 0.0, xl1 = i > 0 ? lxl1 : 0.0;
+            const double yl0 = j > 0 ? lyl0 : 0.0, yl1 = j > 0 ? lyl1 : 0.0;
+            const double zl0 = z > 0 ? lzl0 : 0.0, zl1 = z > 0 ? lzl1 : 0.0;
             double dgd = 0.0, dg1 = 0.0;
             if constexpr (L > 0) graph_div3<R, K, GK, LA>(a, c, we0, we1, dgd, dg1);
             const double fc = double(ld_field(&a.f[c * P + o]));
