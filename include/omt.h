@@ -212,7 +212,11 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
                             omt_batch_handle *out);
 /* Each pair stops at its own first check with residual <= tol (checks every
  * check_every iterations, as omt_solve); infos: host array of B (nullable).
- * Every call starts all B problems from their current iterates.  Environment:
+ * Every call starts all B problems from their current iterates.  As problems
+ * stop, the strips of those still running are re-cut to as few rows as fill
+ * the chip in one round (never more than each problem's default; rows fixed
+ * by the caller or by omt_batch_autotune stay), which changes no iterate.
+ * Environment:
  * OMT_BATCH_PERSISTENT selects the single persistent launch with grid
  * barriers instead of graph-replayed per-iteration launches; OMT_LOG >= 2
  * prints a line to stderr whenever more problems have stopped. */

@@ -1668,6 +1668,8 @@ struct omt_bctx {
     int full_tiles, full_mtiles;    // ... with every problem in them
     int cap_tiles;                  // room of the strip list (one row per strip)
     int resident;                   // workgroups of the persistent kernel the chip holds at once
+    int cus;                        // compute units of the device
+    bool tuned;                     // rows per strip from omt_batch_autotune: kept as they are
     bool comp;
     int dtype;
     int nblocks;
@@ -1828,6 +1830,57 @@ void batch_size_grid(omt_bctx *h)
     h->nblocks = std::max(1, std::min(h->resident, want));
 }
 
+// Step arguments of problem p for every (parity, w buffer, check) variant,
+// relative to the problem's buffers at the start of the solve.
+void batch_fill_args(omt_bctx *h, int p)
+{
+    omt_ctx *c = h->ctx[p];
+    BatchPair &bp = h->pairs[p];
+    const int ncolw = bp.ncolw, rows = c->r.rows, nroww = (c->r.m + rows - 1) / rows;
+    for (int var = 0; var < 8; ++var) {
+        const int par = var / 4, wv = (var / 2) % 2, chk = var % 2;
+        const int ci = (c->cur + par) & 1, wi = (c->wcur + wv) & 1;
+        if (h->dtype == OMT_F64)
+            fill_args(bp.args_mut<double>(var), c, ci, 1 - ci, wi, chk ? 1 - wi : wi, rows, ncolw, nroww, 0);
+        else
+            fill_args(bp.args_mut<float>(var), c, ci, 1 - ci, wi, chk ? 1 - wi : wi, rows, ncolw, nroww, 0);
+    }
+}
+
+// Rows per strip of the problems in the lists: the fewest rows (at most each
+// problem's default) with which all their strips are resident in one round
+// at two waves per SIMD, as for a single problem.  A full batch keeps the
+// default rule; once only a few large problems are left they get more,
+// shorter strips, which the chip would otherwise leave idle.  Rows never
+// change the iterates.  Problems with rows fixed by the caller, and batches
+// tuned by omt_batch_autotune, keep theirs.
+void batch_retile(omt_bctx *h, const std::vector<char> &active)
+{
+    if (h->tuned) return;
+    const int64_t slots = int64_t(h->cus) * 4 * 2;
+    auto strips = [&](int R) {
+        int64_t t = 0;
+        for (int p = 0; p < h->B; ++p) {
+            if (!active[p]) continue;
+            const omt_ctx *c = h->ctx[p];
+            const int rp = c->user_rows > 0 ? c->user_rows : std::min(R, batch_rows_default(c->r.m));
+            t += int64_t(h->pairs[p].ncolw) * ((c->r.m + rp - 1) / rp);
+        }
+        return t;
+    };
+    int R = 1;
+    while (R < 8 && strips(R) > slots) ++R;
+    for (int p = 0; p < h->B; ++p) {
+        omt_ctx *c = h->ctx[p];
+        if (!active[p] || c->user_rows > 0) continue;
+        const int rp = std::min(R, batch_rows_default(c->r.m));
+        if (rp == c->r.rows) continue;
+        c->r.rows = rp;
+        h->pairs[p].ntiles = h->pairs[p].ncolw * ((c->r.m + rp - 1) / rp);
+        batch_fill_args(h, p);
+    }
+}
+
 void batch_drop_graphs(omt_bctx *h)
 {
     for (int q = 0; q < h->ngraphs; ++q) (void)hipGraphExecDestroy(h->graphs[q].exec);
@@ -1911,6 +1964,7 @@ omt_status batch_solve_graphs(omt_bctx *h, BatchArgs ba, int64_t max_iters, int 
                 if (active[p]) live += h->pairs[p].ntiles;
             }
             if (4 * live <= 3 * h->total_tiles) {
+                batch_retile(h, active);
                 HIP_TRY(batch_set_lists(h, active));
                 HIP_TRY(hipMemcpyAsync(h->d_pairs, h->pairs.data(), sizeof(BatchPair) * h->B, hipMemcpyHostToDevice,
                                        h->cap));
@@ -1982,10 +2036,14 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
     }
     // rows per strip: the caller's, else the batched tuner's cached choice
     // for the problem's shape class, else the default rule
+    bool cached = false;
     for (int p = 0; p < B; ++p) {
         omt_ctx *c = h->ctx[p];
         c->user_rows = c->r.rows;
-        if (c->r.rows <= 0) c->r.rows = tune_cache_batch_rows(c);
+        if (c->r.rows <= 0) {
+            c->r.rows = tune_cache_batch_rows(c);
+            cached = cached || c->r.rows > 0;
+        }
         if (c->r.rows <= 0) c->r.rows = batch_rows_default(c->r.m);
     }
     // problem descriptors and the strip / tile lists
@@ -2035,6 +2093,8 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         return fail(OMT_EDEVICE, "batched kernel does not fit on a compute unit");
     }
     h->resident = bpc * cus;
+    h->cus = cus;
+    h->tuned = cached;  // rows from the tuning cache are kept like tuned ones
     batch_size_grid(h);
     *out = h;
     return OMT_OK;
@@ -2050,24 +2110,21 @@ omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, in
         for (int p = 0; p < h->B && infos; ++p) std::memset(&infos[p], 0, sizeof(omt_info));
         return OMT_OK;
     }
-    // step arguments for every (parity, w buffer, check) combination, from
-    // each problem's current buffers
-    for (int p = 0; p < h->B; ++p) {
-        omt_ctx *c = h->ctx[p];
-        BatchPair &bp = h->pairs[p];
-        const int ncolw = bp.ncolw, rows = c->r.rows, nroww = (c->r.m + rows - 1) / rows;
-        for (int var = 0; var < 8; ++var) {
-            const int par = var / 4, wv = (var / 2) % 2, chk = var % 2;
-            const int ci = (c->cur + par) & 1, wi = (c->wcur + wv) & 1;
-            if (h->dtype == OMT_F64)
-                fill_args(bp.args_mut<double>(var), c, ci, 1 - ci, wi, chk ? 1 - wi : wi, rows, ncolw, nroww, 0);
-            else
-                fill_args(bp.args_mut<float>(var), c, ci, 1 - ci, wi, chk ? 1 - wi : wi, rows, ncolw, nroww, 0);
-        }
-    }
+    // rows for the whole batch (a previous solve may have left the rows of
+    // its last problems), then the step arguments for every (parity, w
+    // buffer, check) combination from each problem's current buffers
+    const int full_before = h->full_tiles;
+    const bool persistent = std::getenv("OMT_BATCH_PERSISTENT") != nullptr;
+    if (!persistent) batch_retile(h, std::vector<char>(h->B, 1));
+    for (int p = 0; p < h->B; ++p) batch_fill_args(h, p);
+    int full = 0;
+    for (int p = 0; p < h->B; ++p) full += h->pairs[p].ntiles;
+    h->full_tiles = full;
+    batch_size_grid(h);
     HIP_TRY(hipStreamSynchronize(h->stream));
-    if (h->total_tiles != h->full_tiles || h->total_mtiles != h->full_mtiles) {
-        // a previous solve dropped stopped problems: every problem runs again
+    if (h->total_tiles != h->full_tiles || h->total_mtiles != h->full_mtiles || full != full_before) {
+        // a previous solve dropped stopped problems, or rows changed: every
+        // problem runs again
         HIP_TRY(batch_set_lists(h, std::vector<char>(h->B, 1)));
         batch_drop_graphs(h);
     }
@@ -2085,7 +2142,7 @@ omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, in
     ba.check_every = K;
     ba.max_iters = max_iters;
     ba.tol = tol;
-    if (std::getenv("OMT_BATCH_PERSISTENT")) {
+    if (persistent) {
         omt_status ps = batch_solve_persistent(h, ba);
         if (ps != OMT_OK) return ps;
     } else {
@@ -2263,6 +2320,7 @@ omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, in
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return fail(OMT_EDEVICE, "batch autotune: %s", hipGetErrorString(e));
     h->full_tiles = h->total_tiles;
+    h->tuned = true;
     batch_size_grid(h);
     batch_drop_graphs(h);
     for (int p = 0; p < h->B; ++p) {
