@@ -103,10 +103,11 @@ typedef struct {
     int32_t wnorm;             /* omt_wnorm */
     int32_t dtype;             /* omt_dtype of inputs, outputs and iterates; reductions are FP64 */
     uint32_t flags;            /* OMT_FLAG_* */
-    int32_t tblock;            /* iterations fused per pass over HBM (1, 2, 4, 8); 0: the tuned
-                                  value (omt_autotune, OMT_TUNE_CACHE), else 2 in FP32 on grids
-                                  whose single-iteration strips take 4 or more rows per wave,
-                                  else 1.  Every value gives the same iterates bit for bit. */
+    int32_t tblock;            /* iterations fused per pass over HBM (1, 2, 4, 8; FP64: 1, or 2 for
+                                  k <= 3 without a dense graph); 0: the tuned value (omt_autotune,
+                                  OMT_TUNE_CACHE), else 2 where compiled on grids whose
+                                  single-iteration strips take 4 or more rows per wave, else 1.
+                                  Every value gives the same iterates bit for bit. */
     int32_t rows_per_wave;     /* rows one wavefront streams through; 0 = tuned default */
     double reg_eps;            /* >= 0: quadratic regularisation eps (|u|^2 + |w|^2), Euclidean squares of
                                   all components (Sec. 9); each shrink is then divided by 1 + 2 t eps with

@@ -98,10 +98,19 @@ hipError_t occ_one(int *blocks)
 // iterations per pass in FP32 (not the 9-coordinate complex 3 x 3 kind)
 constexpr bool MAT_T2 = OMT_K <= 6;
 
+// FP64 also runs two iterations per launch for up to three channels on the
+// vector kinds (154 VGPRs at k = 3, the occupancy of one iteration per launch)
+constexpr bool F64_T2 = OMT_K <= 3;
+
 template <int GK, int L>
 hipError_t occ_T(const StepLaunch &Lc, int *blocks)
 {
-    if (Lc.dtype == 1) return occ_one<double, GK, L, 1, false>(blocks);
+    if (Lc.dtype == 1) {
+        if constexpr (F64_T2 && GK != G_DENSE && !is_matrix_kind(GK)) {
+            if (Lc.T == 2) return occ_one<double, GK, L, 2, false>(blocks);
+        }
+        return occ_one<double, GK, L, 1, false>(blocks);
+    }
     if (Lc.T == 1) return Lc.comp ? occ_one<float, GK, L, 1, true>(blocks) : occ_one<float, GK, L, 1, false>(blocks);
     if constexpr (GK == G_MATRIX && MAT_T2) {
         if (Lc.T == 2) return Lc.comp ? occ_one<float, GK, L, 2, true>(blocks) : occ_one<float, GK, L, 2, false>(blocks);
@@ -140,7 +149,7 @@ hipError_t dispatch_met(const StepLaunch &Lc, int ncolw, int ntiles, double *par
 }
 
 // Blocking depths compiled for this channel count (register budget); dense
-// graphs and FP64 run one iteration per launch.
+// graphs run one iteration per launch, FP64 one or two (F64_T2).
 constexpr bool t_ok(int T) { return T == 1 || T == 2 || (T == 4 && OMT_K <= 5) || (T == 8 && OMT_K <= 3); }
 
 template <int GK, int L>
@@ -148,6 +157,9 @@ hipError_t dispatch_T(const StepLaunch &Lc)
 {
     if (Lc.dtype == 1) {
         if (Lc.T == 1 && !Lc.comp) return launch_one<double, GK, L, 1, false>(Lc);
+        if constexpr (F64_T2 && GK != G_DENSE && !is_matrix_kind(GK)) {
+            if (Lc.T == 2 && !Lc.comp) return launch_one<double, GK, L, 2, false>(Lc);
+        }
         return hipErrorInvalidValue;
     }
     if (Lc.T == 1) return Lc.comp ? launch_one<float, GK, L, 1, true>(Lc) : launch_one<float, GK, L, 1, false>(Lc);
@@ -267,7 +279,7 @@ bool OMT_CAT(step_supported_k, OMT_K)(int dtype, int gk, int lb, int T, bool com
     ok = ok || (L_MAT > 0 && gk == G_MATRIX && (lb == L_MAT || (L_MAT2 > 0 && lb == L_MAT2)));
     ok = ok || (L_MAT > 0 && OMT_K != 9 && gk == G_MATNUC && (lb == L_MAT || (L_MAT2 > 0 && lb == L_MAT2)));
     if (!ok) return false;
-    if (dtype == 1) return T == 1 && !comp;
+    if (dtype == 1) return !comp && (T == 1 || (F64_T2 && T == 2 && gk != G_DENSE && !is_matrix_kind(gk)));
     if (gk == G_MATRIX) return T == 1 || (MAT_T2 && T == 2);
     if (gk == G_DENSE || is_matrix_kind(gk)) return T == 1;
     return t_ok(T);

@@ -313,3 +313,35 @@ def test_regularised_with_transfer_active_fp64(unorm, wnorm):
     _cmp_state(gpu_state_np(s), r["state"], 1e-10, "regularised")
     assert abs(info["primal"] - r["primal"]) <= 1e-10 * r["primal"]
     assert abs(info["mass_residual"] - r["mass_residual"]) <= 1e-8 * r["mass_residual"]
+
+
+@pytest.mark.parametrize("k,edges", [(3, I.TRIANGLE), (3, [(0, 1), (1, 2)]), (2, [(0, 1)]), (1, np.zeros((0, 2)))])
+def test_fp64_two_iterations_per_launch_from_active_state(k, edges):
+    """FP64 launches of two iterations (k <= 3) from a state with u and w
+    active: bit-identical to single-iteration launches for several strip
+    heights, and element-wise to 1e-10 of the oracle started from the same
+    state."""
+    torch = cuda()
+    m, n, iters = 77, 200, 24
+    r0, r1 = I.random_pair(28, m, n, k)
+    p = O.Problem(m, n, k, edges=edges, alpha=1.0, tau=3.0)
+    phi, u, w = I.warm_state(6, m, n, k, p.l, u_scale=p.mu, w_scale=50.0 * p.nu, offset=1.0)
+    f, _ = O.prepare_f(r0, r1, p.edges)
+    o = O.solve(p, f, iters, 0.0, 1 << 30, state={"phi": phi, "ux": u[..., 0], "uy": u[..., 1], "w": w})["state"]
+    _assert_active(o, f"fp64 k{k} l{p.l} warm {iters} it", need_w=p.l > 0)
+    note(f"case: fp64 T=2 k{k} l{p.l} from an active state")
+
+    def run(T, rows):
+        s = _solver(torch, r0, r1, edges, "f64", tau=3.0)
+        s.set_state(to_dev(torch, phi, torch.float64), to_dev(torch, u, torch.float64),
+                    to_dev(torch, w, torch.float64) if p.l else None)
+        s.time_steps(T, rows, iters)
+        return s
+
+    a = run(1, 0)
+    sa = a.get_state()
+    for rows in (0, 5, 16):
+        b = run(2, rows).get_state()
+        for key in ("phi", "u", "w"):
+            assert torch.equal(sa[key], b[key]), (k, rows, key)
+    _cmp_state(gpu_state_np(a), o, 1e-10, f"fp64 T=2 k{k}")
