@@ -238,15 +238,15 @@ def bench_batched(a):
         probs.append(dict(rho0=torch.as_tensor(d["rho0"], dtype=dt, device="cuda"),
                           rho1=torch.as_tensor(d["rho1"], dtype=dt, device="cuda"),
                           edges=d["edges"], alpha=d["alpha"], tau=I.tuned_tau(sp["side"], sp["side"]),
-                          compensated=comp))
+                          compensated=comp, tblock=a.tblock))
     print(f"# batched: {len(probs)} pairs, {label}, tol {tol}", file=sys.stderr, flush=True)
     plain = batch = None
     t_plain = t_batch = None
     if a.leg in ("both", "plain"):
         # plain: one solve after another on one stream
         lo, hi = (int(x) for x in a.plain_range.split(":")) if a.plain_range else (0, len(probs))
-        solvers = [omt.Solver(p["rho0"], p["rho1"], p["edges"], alpha=p["alpha"], tau=p["tau"], compensated=comp)
-                   for p in probs[lo:hi]]
+        solvers = [omt.Solver(p["rho0"], p["rho1"], p["edges"], alpha=p["alpha"], tau=p["tau"], compensated=comp,
+                              tblock=p["tblock"]) for p in probs[lo:hi]]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plain = []
@@ -308,7 +308,7 @@ def bench_batched(a):
     return _line(metric, value, unit, sum(its), 0, value * 1e3 / max(its) if unit == "s" else t_batch * 1e3 / max(its),
                  dtype=_dtype_name(dt),
                  config={"workload": f"batched_{a.pairs}_pairs_side64-512_k1or3", "pairs": a.pairs, "tol": tol,
-                         "check_every": 64, "precision": label, "leg": a.leg,
+                         "check_every": 64, "precision": label, "leg": a.leg, "tblock": a.tblock or "default",
                          "plain_range": a.plain_range or None, "parallelism": "single-gpu"},
                  **extra)
 

@@ -199,9 +199,11 @@ omt_status omt_destroy(omt_handle h);
 /* ------------------------------------------------------------- batched */
 
 /* Many independent problems of possibly different sizes, channel counts and
- * graphs solved together: every iteration advances all unfinished pairs in
- * one launch, and the launches of a check interval are replayed as one HIP
- * graph.  params[b], rho0[b], rho1[b] as for omt_create (device pointers);
+ * graphs solved together: each launch advances all unfinished pairs by two
+ * iterations (one HBM pass; the checked iteration and an odd one before it
+ * by one), or by one if any problem sets tblock = 1, and the launches of a
+ * check interval are replayed as one HIP graph.  params[b], rho0[b],
+ * rho1[b] as for omt_create (device pointers);
  * one workspace of omt_batch_workspace_bytes().  Compiled problem types:
  * k = 1 without edges, k = 2 with one edge, k = 3 on the triangle or on the
  * path; anything else is OMT_EUNSUPPORTED.  Every problem of a batch shares

@@ -17,7 +17,8 @@
 // Supported problem types (compiled in): k = 1 without edges, k = 2 with one
 // edge, k = 3 on the complete graph (triangle) or on the path; FP32 (with or
 // without the compensated potential) or FP64, one dtype per batch; one
-// iteration per pass.
+// iteration per pass in the persistent launch, one or two in the launches
+// per iteration.
 
 #include "metrics_device.h"
 
@@ -81,15 +82,15 @@ __device__ bool grid_sync(unsigned *bar, unsigned nblocks)
 // The step arguments are copied out of the table once, before any store, so
 // that the compiler need not reload them after every store it cannot prove
 // disjoint from the table.
-template <typename R, bool COMP>
+template <typename R, bool COMP, int T = 1>
 __device__ __forceinline__ void strip_by_type(int type, const StepArgs<R> &src, int wc, int wr, int lane)
 {
     const StepArgs<R> a = src;
     switch (type) {
-        case 0: process_strip<R, 1, G_NONE, 0, 1, COMP>(a, wc, wr, lane); break;
-        case 1: process_strip<R, 2, G_PATH, 1, 1, COMP>(a, wc, wr, lane); break;
-        case 2: process_strip<R, 3, G_COMPLETE, 3, 1, COMP>(a, wc, wr, lane); break;
-        case 3: process_strip<R, 3, G_PATH, 2, 1, COMP>(a, wc, wr, lane); break;
+        case 0: process_strip<R, 1, G_NONE, 0, T, COMP>(a, wc, wr, lane); break;
+        case 1: process_strip<R, 2, G_PATH, 1, T, COMP>(a, wc, wr, lane); break;
+        case 2: process_strip<R, 3, G_COMPLETE, 3, T, COMP>(a, wc, wr, lane); break;
+        case 3: process_strip<R, 3, G_PATH, 2, T, COMP>(a, wc, wr, lane); break;
         default: break;
     }
 }
@@ -198,17 +199,23 @@ __device__ __forceinline__ int remap_block(int b, int nwg)
     return (x < r) ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
 }
 
-template <typename R, bool COMP>
+// One launch advances every unfinished problem by T iterations: T = 1 walks
+// the list of 64-column strips, T = 2 the list of (64 - 2T)-column strips
+// (pipelined, halo lanes and rows recomputed); var selects the step
+// arguments (T = 1: parity * 4 + w buffer * 2 + check; T = 2: 8 + parity * 2 +
+// w buffer).
+template <typename R, bool COMP, int T>
 __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_step_kernel(const BatchArgs ba, int var)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int t = remap_block(blockIdx.x, gridDim.x) * STEP_WAVES_PER_WG + threadIdx.x / WAVE;
-    if (t >= ba.total_tiles) return;
-    const int p = __builtin_amdgcn_readfirstlane(ba.tile_pair[t]);
+    if (t >= (T == 1 ? ba.total_tiles : ba.total_tiles2)) return;
+    const int p = __builtin_amdgcn_readfirstlane(T == 1 ? ba.tile_pair[t] : ba.tile_pair2[t]);
     if (ba.state[p].done) return;
     const BatchPair &bp = ba.pairs[p];
-    const int local = t - bp.tile0;
-    strip_by_type<R, COMP>(bp.type, bp.template args<R>(var), local % bp.ncolw, local / bp.ncolw, lane);
+    const int ncolw = T == 1 ? bp.ncolw : bp.ncolw2;
+    const int local = t - (T == 1 ? bp.tile0 : bp.tile0_2);
+    strip_by_type<R, COMP, T>(bp.type, bp.template args<R>(var), local % ncolw, local / ncolw, lane);
 }
 
 template <typename R, bool COMP>
@@ -231,9 +238,11 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_metrics_kernel(
 }
 
 // One wave per problem: add up the tiles, count the iterations, decide.
-// last: this check follows the final iteration of the solve.
+// last: this check follows the final iteration of the solve; cur / wcur:
+// the buffers that hold the iterate after this interval, relative to the
+// solve's start.
 __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_decide_kernel(const BatchArgs ba, int iters,
-                                                                                 int last)
+                                                                                 int last, int cur, int wcur)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int p = blockIdx.x * STEP_WAVES_PER_WG + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -249,8 +258,8 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_decide_kernel(c
         const bool bad = !isfinite(R) || !isfinite(m[4]);
         st.iters += iters;
         st.checks += 1;
-        st.cur = int(st.iters & 1);
-        st.wcur = st.checks & 1;
+        st.cur = cur;
+        st.wcur = wcur;
         if (conv || bad || last) {
             st.converged = conv ? 1 : 0;
             st.done = 1;
@@ -261,19 +270,30 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void batch_decide_kernel(c
 
 }  // namespace
 
-hipError_t launch_batch_step(const BatchArgs &a, int dtype, bool comp, int var, hipStream_t s)
+template <int T>
+hipError_t launch_batch_step_T(const BatchArgs &a, int dtype, bool comp, int var, hipStream_t s)
 {
-    const dim3 grid((a.total_tiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG), block(WAVE * STEP_WAVES_PER_WG);
+    const int tiles = T == 1 ? a.total_tiles : a.total_tiles2;
+    if (tiles <= 0) return hipSuccess;
+    const dim3 grid((tiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG), block(WAVE * STEP_WAVES_PER_WG);
     if (dtype == 1)
-        hipLaunchKernelGGL((batch_step_kernel<double, false>), grid, block, 0, s, a, var);
+        hipLaunchKernelGGL((batch_step_kernel<double, false, T>), grid, block, 0, s, a, var);
     else if (comp)
-        hipLaunchKernelGGL((batch_step_kernel<float, true>), grid, block, 0, s, a, var);
+        hipLaunchKernelGGL((batch_step_kernel<float, true, T>), grid, block, 0, s, a, var);
     else
-        hipLaunchKernelGGL((batch_step_kernel<float, false>), grid, block, 0, s, a, var);
+        hipLaunchKernelGGL((batch_step_kernel<float, false, T>), grid, block, 0, s, a, var);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_check(const BatchArgs &a, int dtype, bool comp, int var, int iters, bool last, hipStream_t s)
+hipError_t launch_batch_step(const BatchArgs &a, int dtype, bool comp, int var, hipStream_t s, int T)
+{
+    if (T == 2) return launch_batch_step_T<2>(a, dtype, comp, var, s);
+    if (T != 1) return hipErrorInvalidValue;
+    return launch_batch_step_T<1>(a, dtype, comp, var, s);
+}
+
+hipError_t launch_batch_check(const BatchArgs &a, int dtype, bool comp, int var, int iters, bool last, int cur,
+                              int wcur, hipStream_t s)
 {
     const dim3 grid((a.total_mtiles + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG), block(WAVE * STEP_WAVES_PER_WG);
     if (dtype == 1)
@@ -285,7 +305,7 @@ hipError_t launch_batch_check(const BatchArgs &a, int dtype, bool comp, int var,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nd = (a.B + STEP_WAVES_PER_WG - 1) / STEP_WAVES_PER_WG;
-    hipLaunchKernelGGL(batch_decide_kernel, dim3(nd), block, 0, s, a, iters, last ? 1 : 0);
+    hipLaunchKernelGGL(batch_decide_kernel, dim3(nd), block, 0, s, a, iters, last ? 1 : 0, cur, wcur);
     return hipGetLastError();
 }
 

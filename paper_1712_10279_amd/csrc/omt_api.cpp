@@ -1661,12 +1661,14 @@ struct omt_bctx {
     char *ws;
     BatchPair *d_pairs;
     BatchPairState *d_state;
-    int *d_tile_pair, *d_mtile_pair;
+    int *d_tile_pair, *d_tile_pair2, *d_mtile_pair;
     double *d_partials;
     unsigned *d_bar;
     int total_tiles, total_mtiles;  // strips / metric tiles in the current lists
     int full_tiles, full_mtiles;    // ... with every problem in them
     int cap_tiles;                  // room of the strip list (one row per strip)
+    int total_tiles2;               // strips of two-iteration launches in the current list
+    int T;                          // iterations per launch of the launches per iteration (1 or 2)
     int resident;                   // workgroups of the persistent kernel the chip holds at once
     int cus;                        // compute units of the device
     bool tuned;                     // rows per strip from omt_batch_autotune: kept as they are
@@ -1697,8 +1699,8 @@ int batch_rows_default(int m) { return std::max(2, std::min(8, (m + 31) / 32)); 
 struct BatchLayout {
     std::vector<size_t> off, bytes;
     std::vector<int> mtiles;
-    size_t off_pairs, off_state, off_tp, off_mtp, off_part, off_bar, total;
-    int cap_tiles, total_mtiles;  // strip list sized for one row per strip
+    size_t off_pairs, off_state, off_tp, off_tp2, off_mtp, off_part, off_bar, total;
+    int cap_tiles, cap_tiles2, total_mtiles;  // strip lists sized for one row per strip
 };
 
 omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, bool *comp, int *dtype)
@@ -1706,7 +1708,7 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
     if (B < 1) return fail(OMT_EINVAL, "batch size %d < 1", B);
     if (!params) return fail(OMT_EINVAL, "params is NULL");
     size_t o = 0;
-    L.cap_tiles = L.total_mtiles = 0;
+    L.cap_tiles = L.cap_tiles2 = L.total_mtiles = 0;
     for (int p = 0; p < B; ++p) {
         Resolved r;
         omt_status s = resolve(&params[p], r);
@@ -1725,6 +1727,7 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
         const int ncolw = (r.n + WAVE - 1) / WAVE;
         L.mtiles.push_back(ncolw * ((r.m + MET_ROWS - 1) / MET_ROWS));
         L.cap_tiles += ncolw * r.m;
+        L.cap_tiles2 += (r.n + strip_cols(2) - 1) / strip_cols(2) * r.m;
         L.total_mtiles += L.mtiles.back();
     }
     L.off_pairs = o;
@@ -1733,6 +1736,8 @@ omt_status batch_layout(int32_t B, const omt_params *params, BatchLayout &L, boo
     o += align256(sizeof(BatchPairState) * B);
     L.off_tp = o;
     o += align256(sizeof(int) * size_t(L.cap_tiles));
+    L.off_tp2 = o;
+    o += align256(sizeof(int) * size_t(L.cap_tiles2));
     L.off_mtp = o;
     o += align256(sizeof(int) * L.total_mtiles);
     L.off_part = o;
@@ -1779,16 +1784,30 @@ omt_status batch_solve_persistent(omt_bctx *h, const BatchArgs &ba)
 
 // Enqueue one check interval of nblk iterations: nblk launches that advance
 // every unfinished problem, then the metrics and the decisions.
-hipError_t batch_enqueue_interval(omt_bctx *h, const BatchArgs &ba, int64_t nblk, int par0, int w0, bool last,
+hipError_t batch_enqueue_interval(omt_bctx *h, const BatchArgs &ba, int64_t nblk, int &par, int &wpar, bool last,
                                   hipStream_t s)
 {
+    // par / wpar: phi-u and w buffers of the iterate (relative to the solve's
+    // start) before the interval, and after it on return.  Two iterations
+    // per launch move phi, u and w out of place; single-iteration launches
+    // update w in place except the checked last one, which keeps the old w
+    // for the check.
     hipError_t e = hipSuccess;
-    int var = 0;
-    for (int64_t i = 0; i < nblk && e == hipSuccess; ++i) {
-        var = int((par0 + i) & 1) * 4 + w0 * 2 + (i == nblk - 1 ? 1 : 0);
-        e = launch_batch_step(ba, h->dtype, h->comp, var, s);
+    const int64_t n2 = h->T == 2 ? (nblk - 1) / 2 : 0;
+    for (int64_t q = 0; q < n2 && e == hipSuccess; ++q) {
+        e = launch_batch_step(ba, h->dtype, h->comp, 8 + par * 2 + wpar, s, 2);
+        par ^= 1;
+        wpar ^= 1;
     }
-    if (e == hipSuccess) e = launch_batch_check(ba, h->dtype, h->comp, var, int(nblk), last, s);
+    for (int64_t q = 2 * n2; q < nblk - 1 && e == hipSuccess; ++q) {
+        e = launch_batch_step(ba, h->dtype, h->comp, par * 4 + wpar * 2, s, 1);
+        par ^= 1;
+    }
+    const int var = par * 4 + wpar * 2 + 1;
+    if (e == hipSuccess) e = launch_batch_step(ba, h->dtype, h->comp, var, s, 1);
+    par ^= 1;
+    wpar ^= 1;
+    if (e == hipSuccess) e = launch_batch_check(ba, h->dtype, h->comp, var, int(nblk), last, par, wpar, s);
     return e;
 }
 
@@ -1800,20 +1819,26 @@ hipError_t batch_enqueue_interval(omt_bctx *h, const BatchArgs &ba, int64_t nblk
 // by the caller.
 hipError_t batch_set_lists(omt_bctx *h, const std::vector<char> &active)
 {
-    std::vector<int> tp, mtp;
+    std::vector<int> tp, tp2, mtp;
     for (int p = 0; p < h->B; ++p) {
         BatchPair &bp = h->pairs[p];
         if (!active[p]) continue;
         bp.tile0 = int(tp.size());
+        bp.tile0_2 = int(tp2.size());
         bp.mtile0 = int(mtp.size());
         for (int q = 0; q < bp.ntiles; ++q) tp.push_back(p);
+        if (h->T == 2)
+            for (int q = 0; q < bp.ntiles2; ++q) tp2.push_back(p);
         for (int q = 0; q < bp.mtiles; ++q) mtp.push_back(p);
     }
     h->total_tiles = int(tp.size());
+    h->total_tiles2 = int(tp2.size());
     h->total_mtiles = int(mtp.size());
     hipError_t e = hipSuccess;
     if (!tp.empty())
         e = hipMemcpyAsync(h->d_tile_pair, tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, h->cap);
+    if (e == hipSuccess && !tp2.empty())
+        e = hipMemcpyAsync(h->d_tile_pair2, tp2.data(), sizeof(int) * tp2.size(), hipMemcpyHostToDevice, h->cap);
     if (e == hipSuccess && !mtp.empty())
         e = hipMemcpyAsync(h->d_mtile_pair, mtp.data(), sizeof(int) * mtp.size(), hipMemcpyHostToDevice, h->cap);
     // the host vectors go out of scope: finish the copies first
@@ -1845,6 +1870,15 @@ void batch_fill_args(omt_bctx *h, int p)
         else
             fill_args(bp.args_mut<float>(var), c, ci, 1 - ci, wi, chk ? 1 - wi : wi, rows, ncolw, nroww, 0);
     }
+    // two iterations per launch: phi, u and w all out of place
+    for (int var = 8; var < 12 && h->T == 2; ++var) {
+        const int par = (var - 8) / 2, wv = (var - 8) % 2;
+        const int ci = (c->cur + par) & 1, wi = (c->wcur + wv) & 1;
+        if (h->dtype == OMT_F64)
+            fill_args(bp.args_mut<double>(var), c, ci, 1 - ci, wi, 1 - wi, rows, bp.ncolw2, nroww, 0);
+        else
+            fill_args(bp.args_mut<float>(var), c, ci, 1 - ci, wi, 1 - wi, rows, bp.ncolw2, nroww, 0);
+    }
 }
 
 // Rows per strip of the problems in the lists: the fewest rows (at most each
@@ -1864,7 +1898,7 @@ void batch_retile(omt_bctx *h, const std::vector<char> &active)
             if (!active[p]) continue;
             const omt_ctx *c = h->ctx[p];
             const int rp = c->user_rows > 0 ? c->user_rows : std::min(R, batch_rows_default(c->r.m));
-            t += int64_t(h->pairs[p].ncolw) * ((c->r.m + rp - 1) / rp);
+            t += int64_t(h->T == 2 ? h->pairs[p].ncolw2 : h->pairs[p].ncolw) * ((c->r.m + rp - 1) / rp);
         }
         return t;
     };
@@ -1877,6 +1911,7 @@ void batch_retile(omt_bctx *h, const std::vector<char> &active)
         if (rp == c->r.rows) continue;
         c->r.rows = rp;
         h->pairs[p].ntiles = h->pairs[p].ncolw * ((c->r.m + rp - 1) / rp);
+        h->pairs[p].ntiles2 = h->pairs[p].ncolw2 * ((c->r.m + rp - 1) / rp);
         batch_fill_args(h, p);
     }
 }
@@ -1892,14 +1927,14 @@ omt_status batch_solve_graphs(omt_bctx *h, BatchArgs ba, int64_t max_iters, int 
     HIP_TRY(launch_zero(h->d_state, sizeof(BatchPairState) * h->B, h->cap));
     HIP_TRY(launch_zero(h->d_bar, sizeof(unsigned) * BAR_WORDS, h->cap));
     int64_t done = 0;
-    int nchecks = 0;
     unsigned stopped = 0;
     const bool verbose = log_level() >= 2;
     auto last_note = std::chrono::steady_clock::now();
+    int par = 0, wpar = 0;  // buffers of the iterate, relative to the solve's start
     while (done < max_iters && stopped < unsigned(h->B)) {
         const int64_t nblk = std::min<int64_t>(K, max_iters - done);
         const bool last = done + nblk == max_iters;
-        const int par0 = int(done & 1), w0 = nchecks & 1;
+        const int par0 = par, w0 = wpar;
         if (nblk == K && !last) {
             omt_bctx::Graph *g = nullptr;
             for (int q = 0; q < h->ngraphs; ++q)
@@ -1914,7 +1949,8 @@ omt_status batch_solve_graphs(omt_bctx *h, BatchArgs ba, int64_t max_iters, int 
                 }
                 hipGraph_t graph = nullptr;
                 HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-                hipError_t e = batch_enqueue_interval(h, ba, K, par0, w0, false, h->cap);
+                int pc = par0, wc = w0;
+                hipError_t e = batch_enqueue_interval(h, ba, K, pc, wc, false, h->cap);
                 hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
                 if (e != hipSuccess || e2 != hipSuccess) {
                     if (graph) (void)hipGraphDestroy(graph);
@@ -1933,10 +1969,15 @@ omt_status batch_solve_graphs(omt_bctx *h, BatchArgs ba, int64_t max_iters, int 
             }
             HIP_TRY(hipGraphLaunch(g->exec, h->cap));
         } else {
-            HIP_TRY(batch_enqueue_interval(h, ba, nblk, par0, w0, last, h->cap));
+            int pc = par0, wc = w0;
+            HIP_TRY(batch_enqueue_interval(h, ba, nblk, pc, wc, last, h->cap));
         }
+        // buffers after the interval: each launch moves phi and u, the
+        // two-iteration launches and the checked launch also move w
+        const int64_t n2 = h->T == 2 ? (nblk - 1) / 2 : 0, n1 = nblk - 1 - 2 * n2;
+        par ^= int((n2 + n1 + 1) & 1);
+        wpar ^= int((n2 + 1) & 1);
         done += nblk;
-        ++nchecks;
         HIP_TRY(hipMemcpyAsync(h->host_stopped, h->d_bar + 3, sizeof(unsigned), hipMemcpyDeviceToHost, h->cap));
         HIP_TRY(hipStreamSynchronize(h->cap));
         if (verbose) {
@@ -1971,6 +2012,7 @@ omt_status batch_solve_graphs(omt_bctx *h, BatchArgs ba, int64_t max_iters, int 
                 HIP_TRY(hipStreamSynchronize(h->cap));
                 batch_drop_graphs(h);
                 ba.total_tiles = h->total_tiles;
+                ba.total_tiles2 = h->total_tiles2;
                 ba.total_mtiles = h->total_mtiles;
             }
         }
@@ -2020,6 +2062,7 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
     h->d_pairs = reinterpret_cast<BatchPair *>(h->ws + L.off_pairs);
     h->d_state = reinterpret_cast<BatchPairState *>(h->ws + L.off_state);
     h->d_tile_pair = reinterpret_cast<int *>(h->ws + L.off_tp);
+    h->d_tile_pair2 = reinterpret_cast<int *>(h->ws + L.off_tp2);
     h->d_mtile_pair = reinterpret_cast<int *>(h->ws + L.off_mtp);
     h->d_partials = reinterpret_cast<double *>(h->ws + L.off_part);
     h->d_bar = reinterpret_cast<unsigned *>(h->ws + L.off_bar);
@@ -2046,10 +2089,18 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         }
         if (c->r.rows <= 0) c->r.rows = batch_rows_default(c->r.m);
     }
+    // two iterations per launch (outside the checked ones) when every problem
+    // has them compiled and none asks for one per launch (tblock 1)
+    bool t2 = true;
+    for (int p = 0; p < B; ++p) {
+        const Resolved &r = h->ctx[p]->r;
+        if (r.tblock == 1 || !step_supported(r.dtype, r.k, r.gk, r.lb, 2, r.comp)) t2 = false;
+    }
+    h->T = t2 ? 2 : 1;
     // problem descriptors and the strip / tile lists
-    std::vector<int> tp, mtp;
+    std::vector<int> tp, tp2, mtp;
     h->pairs.resize(B);
-    int t0 = 0, m0 = 0;
+    int t0 = 0, t02 = 0, m0 = 0;
     for (int p = 0; p < B; ++p) {
         omt_ctx *c = h->ctx[p];
         BatchPair &bp = h->pairs[p];
@@ -2060,6 +2111,9 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         bp.ncolw = ncolw;
         bp.tile0 = t0;
         bp.ntiles = ncolw * ((c->r.m + c->r.rows - 1) / c->r.rows);
+        bp.ncolw2 = (c->r.n + strip_cols(2) - 1) / strip_cols(2);
+        bp.tile0_2 = t02;
+        bp.ntiles2 = bp.ncolw2 * ((c->r.m + c->r.rows - 1) / c->r.rows);
         bp.mcolw = ncolw;
         bp.mtile0 = m0;
         bp.mtiles = L.mtiles[p];
@@ -2068,13 +2122,19 @@ omt_status omt_batch_create(int32_t B, const omt_params *params, const void *con
         bp.tau = c->r.tau;
         bp.R0 = c->r.tau * c->fnorm2;
         for (int q = 0; q < bp.ntiles; ++q) tp.push_back(p);
+        if (h->T == 2)
+            for (int q = 0; q < bp.ntiles2; ++q) tp2.push_back(p);
         for (int q = 0; q < L.mtiles[p]; ++q) mtp.push_back(p);
         t0 += bp.ntiles;
+        t02 += h->T == 2 ? bp.ntiles2 : 0;
         m0 += L.mtiles[p];
     }
     h->total_tiles = h->full_tiles = t0;
+    h->total_tiles2 = t02;
     h->st.resize(B);
     hipError_t e = hipMemcpyAsync(h->d_tile_pair, tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && !tp2.empty())
+        e = hipMemcpyAsync(h->d_tile_pair2, tp2.data(), sizeof(int) * tp2.size(), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_mtile_pair, mtp.data(), sizeof(int) * mtp.size(), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -2133,11 +2193,13 @@ omt_status omt_batch_solve(omt_batch_handle h, int64_t max_iters, double tol, in
     ba.pairs = h->d_pairs;
     ba.state = h->d_state;
     ba.tile_pair = h->d_tile_pair;
+    ba.tile_pair2 = h->d_tile_pair2;
     ba.mtile_pair = h->d_mtile_pair;
     ba.partials = h->d_partials;
     ba.bar = h->d_bar;
     ba.B = h->B;
     ba.total_tiles = h->total_tiles;
+    ba.total_tiles2 = h->total_tiles2;
     ba.total_mtiles = h->total_mtiles;
     ba.check_every = K;
     ba.max_iters = max_iters;
@@ -2248,6 +2310,7 @@ omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, in
     ba.pairs = h->d_pairs;
     ba.state = h->d_state;
     ba.tile_pair = h->d_tile_pair;
+    ba.tile_pair2 = h->d_tile_pair2;
     ba.mtile_pair = h->d_mtile_pair;
     ba.partials = h->d_partials;
     ba.bar = h->d_bar;
@@ -2264,6 +2327,7 @@ omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, in
         BatchPair &bp = h->pairs[p];
         c->r.rows = R;
         bp.ntiles = bp.ncolw * ((c->r.m + R - 1) / R);
+        bp.ntiles2 = bp.ncolw2 * ((c->r.m + R - 1) / R);
         const int nroww = (c->r.m + R - 1) / R, ci = c->cur, wi = c->wcur;
         if (h->dtype == OMT_F64)
             fill_args(bp.args_mut<double>(1), c, ci, 1 - ci, wi, 1 - wi, R, bp.ncolw, nroww, 0);
@@ -2276,6 +2340,7 @@ omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, in
         if (e == hipSuccess)
             e = hipMemcpyAsync(h->d_pairs, h->pairs.data(), sizeof(BatchPair) * h->B, hipMemcpyHostToDevice, h->cap);
         ba.total_tiles = h->total_tiles;
+        ba.total_tiles2 = h->total_tiles2;
         if (e == hipSuccess) e = launch_batch_step(ba, h->dtype, h->comp, 1, h->cap);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, h->cap);
         for (int q = 0; q < n && e == hipSuccess; ++q) e = launch_batch_step(ba, h->dtype, h->comp, 1, h->cap);

@@ -125,8 +125,10 @@ hipError_t launch_quads_to_tiles(const double *qpart, int64_t qstride, int nq, i
 // arguments for the iteration parity par (potential / flux buffers), the
 // current w buffer and whether the iteration is a check (w out of place).
 struct BatchPair {
-    // step arguments of the batch's dtype (StepArgs<float> or <double>)
-    alignas(16) unsigned char v[8][sizeof(StepArgs<double>)];
+    // step arguments of the batch's dtype (StepArgs<float> or <double>): 8
+    // single-iteration variants (parity, w buffer, check), then 4 for two
+    // iterations per launch (parity, w buffer)
+    alignas(16) unsigned char v[12][sizeof(StepArgs<double>)];
     template <typename R>
     __host__ __device__ const StepArgs<R> &args(int var) const
     {
@@ -138,8 +140,9 @@ struct BatchPair {
         return *reinterpret_cast<StepArgs<R> *>(v[var]);
     }
     int type, l;
-    int ncolw, tile0, ntiles;   // step strips: across, first in the list, count
-    int mcolw, mtile0, mtiles;  // metric tiles likewise
+    int ncolw, tile0, ntiles;      // step strips: across, first in the list, count
+    int ncolw2, tile0_2, ntiles2;  // strips of two-iteration launches likewise
+    int mcolw, mtile0, mtiles;     // metric tiles likewise
     double mu, nu, tau, R0;
 };
 
@@ -153,10 +156,10 @@ struct BatchPairState {
 struct BatchArgs {
     const BatchPair *pairs;
     BatchPairState *state;
-    const int *tile_pair, *mtile_pair;
+    const int *tile_pair, *tile_pair2, *mtile_pair;
     double *partials;
     unsigned *bar;  // barrier words, BAR_WORDS of them (see grid_sync in batch.hip)
-    int B, total_tiles, total_mtiles, check_every;
+    int B, total_tiles, total_tiles2, total_mtiles, check_every;
     int64_t max_iters;
     double tol;
 };
@@ -168,12 +171,14 @@ int batch_type(int k, int gk, int lb);  // -1 if not compiled into the batched k
 // dtype: 0 FP32 (comp: compensated potential), 1 FP64
 hipError_t batch_blocks_per_cu(int dtype, bool comp, int *blocks);
 hipError_t launch_batch(const BatchArgs &a, int dtype, bool comp, int nblocks, hipStream_t s);
-// one iteration of every unfinished problem; var = par * 4 + wcur * 2 + check
-hipError_t launch_batch_step(const BatchArgs &a, int dtype, bool comp, int var, hipStream_t s);
+// T iterations (1 or 2) of every unfinished problem; var = par * 4 + wcur * 2 +
+// check for T = 1, 8 + par * 2 + wcur for T = 2
+hipError_t launch_batch_step(const BatchArgs &a, int dtype, bool comp, int var, hipStream_t s, int T = 1);
 // metrics tiles and per-problem decisions after a check iteration (iters =
-// iterations since the previous check; last = the solve ends here)
-hipError_t launch_batch_check(const BatchArgs &a, int dtype, bool comp, int var, int iters, bool last,
-                              hipStream_t s);
+// iterations since the previous check; last = the solve ends here; cur /
+// wcur = buffers of the iterate after it, relative to the solve's start)
+hipError_t launch_batch_check(const BatchArgs &a, int dtype, bool comp, int var, int iters, bool last, int cur,
+                              int wcur, hipStream_t s);
 
 // ---------------------------------------------------------------- auxiliary
 
