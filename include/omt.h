@@ -261,7 +261,9 @@ omt_status omt_autotune(omt_handle h, int32_t iters_per_trial, int32_t *best_t, 
 
 /* Launch exactly n iterations of the step kernel with the given blocking
  * depth (T must divide n) and report the mean time per launch in
- * microseconds measured with HIP events on the handle's stream.  For
+ * microseconds, measured with HIP events around one replay of the launches
+ * captured as a HIP graph (the way the solve runs its check intervals), on
+ * the handle's private stream after the work already on its stream.  For
  * measurement; the state advances by n iterations.  One more launch,
  * untimed, precedes them so that the queue is busy when the timed region
  * opens; it writes only the buffers the first timed launch overwrites. */

@@ -1484,29 +1484,57 @@ omt_status omt_time_steps(omt_handle h, int32_t T, int32_t rows_per_wave, int64_
     if (T < 1 || n < T || n % T != 0) return fail(OMT_EINVAL, "need T >= 1 dividing n (T %d, n %lld)", T, (long long)n);
     if (rows_per_wave < 0) return fail(OMT_EINVAL, "rows_per_wave < 0");
     const int rows = rows_per_wave > 0 ? rows_per_wave : default_rows(h, T);
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    // an untimed launch first, so that the queue is busy when the timed
-    // region opens: it reads the current iterate and writes the other
-    // buffers (w out of place) without making them current, so the timed
-    // launches start from the caller's state
+    // The timed launches are captured into a HIP graph and replayed once on
+    // the handle's private stream, as the solve replays its check
+    // intervals, so that the time is that of the kernels back to back and not
+    // of the host's launch rate.  An untimed launch goes first, so that the
+    // queue is busy when the timed region opens: it reads the current iterate
+    // and writes the other buffers (w out of place) without making them
+    // current, so the timed launches start from the caller's state.
+    if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamSynchronize(h->stream));
     const int c0 = h->cur, w0 = h->wcur;
     const int64_t it0 = h->iters_done;
-    omt_status s = step_launch(h, T, rows, false);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    omt_status s = OMT_OK;
+    for (int64_t q = 0; q < n / T && s == OMT_OK; ++q) s = step_launch(h, T, rows, T == 1, h->cap);
+    hipError_t e = hipStreamEndCapture(h->cap, &graph);
+    const int c1 = h->cur, w1 = h->wcur;
+    const int64_t it1 = h->iters_done;
     h->cur = c0;
     h->wcur = w0;
     h->iters_done = it0;
-    if (s != OMT_OK) return s;
-    HIP_TRY(hipEventRecord(e0, h->stream));
-    for (int64_t q = 0; q < n / T && s == OMT_OK; ++q) s = step_launch(h, T, rows, T == 1);
-    HIP_TRY(hipEventRecord(e1, h->stream));
-    HIP_TRY(hipEventSynchronize(e1));
+    if (s == OMT_OK && e == hipSuccess) e = hipGraphInstantiateWithFlags(&exec, graph, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (s != OMT_OK || e != hipSuccess) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        return s != OMT_OK ? s : fail(OMT_EDEVICE, "timed launches: %s", hipGetErrorString(e));
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) {
+        s = step_launch(h, T, rows, false, h->cap);
+        h->cur = c0;
+        h->wcur = w0;
+        h->iters_done = it0;
+    }
+    if (e == hipSuccess && s == OMT_OK) e = hipEventRecord(e0, h->cap);
+    if (e == hipSuccess && s == OMT_OK) e = hipGraphLaunch(exec, h->cap);
+    if (e == hipSuccess && s == OMT_OK) e = hipEventRecord(e1, h->cap);
+    if (e == hipSuccess && s == OMT_OK) e = hipEventSynchronize(e1);
     float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e == hipSuccess && s == OMT_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipGraphExecDestroy(exec);
     if (s != OMT_OK) return s;
+    if (e != hipSuccess) return fail(OMT_EDEVICE, "timed launches: %s", hipGetErrorString(e));
+    h->cur = c1;
+    h->wcur = w1;
+    h->iters_done = it1;
     h->have_last = false;
     if (us_per_launch) *us_per_launch = 1000.0 * double(ms) / double(n / T);
     return OMT_OK;

@@ -205,6 +205,17 @@ def test_large_grid_cones_from_active_state_fp64():
     _cones(torch, d, "f64", 24, [(1, 0), (1, 3)], tol)
 
 
+def test_loss_grid_cones_fp64_two_iterations_per_launch():
+    """512 x 512, k = 3 triangle, tau 1024 (the loss workload's problem),
+    FP64 from an active state: two iterations per launch (the default strips
+    and 5-row strips) and single-iteration launches give identical bits and
+    match the oracle's cones to 1e-10."""
+    torch = cuda()
+    d = I.loss_512(0)
+    note("case: 512x512 k3 triangle fp64, warm active state, 24 it, shapes T2 / T2 r5 / T1")
+    _cones(torch, d, "f64", 24, [(2, 0), (2, 5), (1, 0)], {key: 1e-10 for key in ("phi", "ux", "uy", "w")})
+
+
 @pytest.mark.parametrize("k,edges", [(3, I.TRIANGLE), (3, [(0, 1), (1, 2)]), (5, I.path_edges(5)),
                                      (8, I.path_edges(8)), (2, [(0, 1)]), (1, np.zeros((0, 2)))])
 @pytest.mark.parametrize("comp", [False, True])

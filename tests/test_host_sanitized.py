@@ -55,3 +55,10 @@ def test_host_code_clean_under_sanitizers(tmp_path):
     run = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=300)
     assert run.returncode == 0, (run.stdout + run.stderr)[-3000:]
     assert "0 failure(s)" in run.stdout
+    assert "omt:" not in run.stderr
+    # OMT_LOG=1: every refused call prints its status and detail on stderr
+    run = subprocess.run([str(exe)], capture_output=True, text=True, env=dict(env, OMT_LOG="1"), timeout=300)
+    assert run.returncode == 0, (run.stdout + run.stderr)[-3000:]
+    for line in ("omt: invalid argument: grid must be at least 2 x 2", "omt: invalid channel graph:",
+                 "omt: step sizes violate the convergence condition:", "omt: workspace too small:"):
+        assert line in run.stderr, line
