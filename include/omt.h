@@ -106,7 +106,8 @@ typedef struct {
     int32_t tblock;            /* iterations fused per pass over HBM (1, 2, 4, 8; FP64: 1, or 2 for
                                   k <= 3 without a dense graph); 0: the tuned value (omt_autotune,
                                   OMT_TUNE_CACHE), else 2 where compiled on grids whose
-                                  single-iteration strips take 4 or more rows per wave, else 1.
+                                  single-iteration strips take 4 or more rows per wave (2 or more
+                                  in FP64), else 1.
                                   Every value gives the same iterates bit for bit. */
     int32_t rows_per_wave;     /* rows one wavefront streams through; 0 = tuned default */
     double reg_eps;            /* >= 0: quadratic regularisation eps (|u|^2 + |w|^2), Euclidean squares of

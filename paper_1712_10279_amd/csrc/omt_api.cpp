@@ -807,11 +807,15 @@ int tblock_of(const omt_ctx *h)
     if (h->r.tblock > 0) return h->r.tblock;
     if (h->tuned_T > 0) return h->tuned_T;
     // untuned: two iterations per HBM pass where single-iteration strips
-    // are tall (large grids), when compiled.  Measured with the autotuner's
-    // best shape against T = 1: 1.21x at 1024^2 k = 8, 1.36x at 2048^2
-    // k = 8, 1.31x at 1024^2 k = 3, 1.36x at 1024^2 k = 1; a tie at 512^2
-    // k = 8 (2 rows per wave) and none at 256^2 (1 row)
-    if (rule_rows(h, 1) >= 4 && step_supported(h->r.dtype, h->r.k, h->r.gk, h->r.lb, 2, h->r.comp)) return 2;
+    // are tall (large grids), when compiled.  FP32, measured with the
+    // autotuner's best shape against T = 1: 1.21x at 1024^2 k = 8, 1.36x at
+    // 2048^2 k = 8, 1.31x at 1024^2 k = 3, 1.36x at 1024^2 k = 1; a tie at
+    // 512^2 k = 8 (2 rows per wave) and none at 256^2 (1 row).  FP64 (k <= 3)
+    // gains already at 2 rows: with the rule's rows 1.16x at 384^2 k = 3,
+    // 1.28x at 384^2 k = 1, 1.05x at 512^2 k = 3, 1.18x at 512^2 k = 1, a tie
+    // at 320^2 (1 row) and a loss at 256^2
+    const int tall = h->r.dtype == OMT_F64 ? 2 : 4;
+    if (rule_rows(h, 1) >= tall && step_supported(h->r.dtype, h->r.k, h->r.gk, h->r.lb, 2, h->r.comp)) return 2;
     return 1;
 }
 

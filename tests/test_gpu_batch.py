@@ -171,3 +171,25 @@ def test_batch_autotune_keeps_bits_and_caches_rows(mode, tmp_path, monkeypatch):
     rows2, us2 = b2.autotune(0)
     assert us2 == 0.0
     assert rows2[:1] + rows2[2:] == rows[:1] + rows[2:]
+
+
+@pytest.mark.parametrize("check_every,iters", [(7, 23), (8, 30), (5, 11), (2, 9)])
+def test_batch_interval_schedules_bit_identical(check_every, iters):
+    """Check intervals of every parity (two-iteration launches, an odd
+    single one, the checked one; a short last interval): each problem of
+    the batch ends with the bits and checks of its own solve."""
+    torch = cuda()
+    from paper_1712_10279_amd import omt
+    probs = _problems(torch, 80, dtype=torch.float64)
+    note(f"case: batch intervals of {check_every}, {iters} iterations")
+    b = omt.BatchSolver(probs)
+    infos = b.solve(iters, 0.0, check_every)
+    for q, pr in enumerate(probs):
+        kw = {key: v for key, v in pr.items() if key not in ("rho0", "rho1", "edges")}
+        s = omt.Solver(pr["rho0"], pr["rho1"], pr["edges"], **kw)
+        info = s.solve(iters, 0.0, check_every)
+        assert infos[q]["iters"] == info["iters"] == iters and infos[q]["checks"] == info["checks"]
+        assert infos[q]["residual"] == info["residual"]
+        gs, bs = s.get_state(), b.get_state(q)
+        for key in ("phi", "u", "w"):
+            assert torch.equal(gs[key], bs[key]), (q, key)
