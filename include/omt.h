@@ -235,15 +235,16 @@ omt_status omt_batch_set_state(omt_batch_handle h, int32_t b, const void *phi, c
 /* Choose the rows per strip of the batched step kernel for every shape class
  * of the batch (problems with the same grid and compiled type): each
  * candidate is timed over launches_per_trial launches (at least 4, HIP
- * events on the batch's private stream) of that class alone, reading the
- * current iterates without changing them.  Problems whose rows_per_wave the
+ * events on the batch's private stream) of that class alone, in the launch
+ * shape the batch's solves run (two iterations per launch when they do),
+ * reading the current iterates without changing them.  Problems whose rows_per_wave the
  * caller fixed keep it.  The choice is kept in the handle (the next
  * omt_batch_solve uses it) and in the tuning cache under "batch <class>"
  * (OMT_TUNE_CACHE), where omt_batch_create finds it.  Rows never change the
  * iterates: every problem stays bit-identical to its own omt_solve.
  * rows: host array of B (nullable), the rows chosen per problem;
  * us_per_iter (nullable): one batched iteration of all B problems with the
- * chosen rows, in microseconds.  launches_per_trial = 0 tunes nothing and
+ * chosen rows, in microseconds (a two-iteration launch counts as two).  launches_per_trial = 0 tunes nothing and
  * only reports the rows in use (us_per_iter 0).  Not for use while a solve
  * of this handle runs on another thread. */
 omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, int32_t *rows, double *us_per_iter);

@@ -2351,9 +2351,12 @@ omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, in
     ba.check_every = 64;
     ba.max_iters = 1;
     ba.tol = 0.0;
-    // the timed launches use variant 1 of the step arguments (read the
-    // current phi, u, w; write phi and u to the other ping-pong buffer and
-    // w out of place), so the current iterates are never changed
+    // the timed launches are the ones the batch's solves run (two
+    // iterations per launch when the batch does): variant 1 of the step
+    // arguments, or variant 8 for two iterations (read the current phi, u,
+    // w; write all three to the other buffers), so the current iterates are
+    // never changed
+    const int tv = h->T == 2 ? 8 : 1;
     auto set_rows = [&](int p, int R) {
         omt_ctx *c = h->ctx[p];
         BatchPair &bp = h->pairs[p];
@@ -2361,10 +2364,11 @@ omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, in
         bp.ntiles = bp.ncolw * ((c->r.m + R - 1) / R);
         bp.ntiles2 = bp.ncolw2 * ((c->r.m + R - 1) / R);
         const int nroww = (c->r.m + R - 1) / R, ci = c->cur, wi = c->wcur;
+        const int ncw = tv == 8 ? bp.ncolw2 : bp.ncolw;
         if (h->dtype == OMT_F64)
-            fill_args(bp.args_mut<double>(1), c, ci, 1 - ci, wi, 1 - wi, R, bp.ncolw, nroww, 0);
+            fill_args(bp.args_mut<double>(tv), c, ci, 1 - ci, wi, 1 - wi, R, ncw, nroww, 0);
         else
-            fill_args(bp.args_mut<float>(1), c, ci, 1 - ci, wi, 1 - wi, R, bp.ncolw, nroww, 0);
+            fill_args(bp.args_mut<float>(tv), c, ci, 1 - ci, wi, 1 - wi, R, ncw, nroww, 0);
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto timed = [&](const std::vector<char> &active, double *us) -> hipError_t {
@@ -2373,14 +2377,14 @@ omt_status omt_batch_autotune(omt_batch_handle h, int32_t launches_per_trial, in
             e = hipMemcpyAsync(h->d_pairs, h->pairs.data(), sizeof(BatchPair) * h->B, hipMemcpyHostToDevice, h->cap);
         ba.total_tiles = h->total_tiles;
         ba.total_tiles2 = h->total_tiles2;
-        if (e == hipSuccess) e = launch_batch_step(ba, h->dtype, h->comp, 1, h->cap);  // warm-up
+        if (e == hipSuccess) e = launch_batch_step(ba, h->dtype, h->comp, tv, h->cap, h->T);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, h->cap);
-        for (int q = 0; q < n && e == hipSuccess; ++q) e = launch_batch_step(ba, h->dtype, h->comp, 1, h->cap);
+        for (int q = 0; q < n && e == hipSuccess; ++q) e = launch_batch_step(ba, h->dtype, h->comp, tv, h->cap, h->T);
         if (e == hipSuccess) e = hipEventRecord(e1, h->cap);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        *us = 1000.0 * double(ms) / n;
+        *us = 1000.0 * double(ms) / (double(n) * h->T);  // per iteration
         return e;
     };
     HIP_TRY(hipStreamSynchronize(h->stream));
