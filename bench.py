@@ -42,7 +42,9 @@ def _parse():
     ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0: library default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations for the CPU baseline (0: auto)")
-    ap.add_argument("--timing-launches", type=int, default=200)
+    ap.add_argument("--timing-launches", type=int, default=200,
+                    help="iterations of step launches timed for the roofline (launches of T iterations each: "
+                         "T = 2 times half as many launches)")
     ap.add_argument("--workload", default="large", choices=["large", "batched", "rgb", "loss", "matrix", "volume"],
                     help="large: 1024x1024 k=8 throughput (default); batched: 96 pairs to 1e-5, batched vs "
                          "plain; rgb: 256x256 k=3 time to 1e-5; loss: 8 pairs of 512x512 forward+backward; "
@@ -109,16 +111,18 @@ def _traffic(key, rows=0, files=STEP_SOURCES):
     return e.get("bytes_per_launch")
 
 
-def _timed_from_active_state(s, edges, alpha, tau, T, rows, launches, chunk_iters=32):
+def _timed_from_active_state(s, edges, alpha, tau, T, rows, iters, chunk_iters=32):
     """Time the step kernel (HIP events on the solver's stream, omt_time_steps)
     from a seeded synthetic state in which the flux and transfer shrinks are
     active on most pixels (inputs.warm_state, scaled by the resolved mu and
     nu), so that the measurement never sits in the regime where every shrink
     returns zero.  The iteration relaxes the channel differences of such a
     state within a few hundred iterations (w returns to zero where the data
-    need no transfer), so the state is loaded again before every
-    ``chunk_iters`` iterations of timed launches.  Returns (mean us per
-    launch, activity of the state after the last timed launch)."""
+    need no transfer), so the state is loaded again before every chunk of
+    chunk_iters // T iterations (one graph replay of chunk_iters // T^2
+    launches); about ``iters`` iterations are timed in all (iters / T
+    launches).  Returns (mean us per launch, activity of the state after the
+    last timed launch)."""
     import torch
     from paper_1712_10279_amd import inputs as I
     from paper_1712_10279_amd import omt
@@ -130,7 +134,7 @@ def _timed_from_active_state(s, edges, alpha, tau, T, rows, launches, chunk_iter
     phi, u, w = dev(phi), dev(u), dev(w) if l else None
     per = max(1, chunk_iters // T)
     times = []
-    for _ in range(max(1, launches // per)):
+    for _ in range(max(1, iters // per)):
         s.set_state(phi, u, w)
         times.append(s.time_steps(T, rows, per))
     return sum(times) / len(times), _activity(s)
