@@ -8,11 +8,29 @@ namespace omt {
 namespace dev {
 
 // ------------------------------------------------------------ lane moves
-
-__device__ __forceinline__ float lane_next(float v) { return __shfl_down(v, 1u, WAVE); }
-__device__ __forceinline__ float lane_prev(float v) { return __shfl_up(v, 1u, WAVE); }
-__device__ __forceinline__ double lane_next(double v) { return __shfl_down(v, 1u, WAVE); }
-__device__ __forceinline__ double lane_prev(double v) { return __shfl_up(v, 1u, WAVE); }
+//
+// The value of the neighbouring lane (column), by a DPP wavefront shift of
+// one lane: a modifier of a vector move, with no round trip through the LDS
+// crossbar and no counter to wait on.  A lane with no neighbour (lane 63
+// for lane_next, lane 0 for lane_prev) keeps its own value, as a shuffle
+// that leaves the wave does.
+constexpr int DPP_WAVE_SHL1 = 0x130;  // lane l reads lane l + 1
+constexpr int DPP_WAVE_SHR1 = 0x138;  // lane l reads lane l - 1
+template <int CTRL>
+__device__ __forceinline__ int dpp_shift(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float lane_next(float v) { return __int_as_float(dpp_shift<DPP_WAVE_SHL1>(__float_as_int(v))); }
+__device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_shift<DPP_WAVE_SHR1>(__float_as_int(v))); }
+__device__ __forceinline__ double lane_next(double v)
+{
+    return __hiloint2double(dpp_shift<DPP_WAVE_SHL1>(__double2hiint(v)), dpp_shift<DPP_WAVE_SHL1>(__double2loint(v)));
+}
+__device__ __forceinline__ double lane_prev(double v)
+{
+    return __hiloint2double(dpp_shift<DPP_WAVE_SHR1>(__double2hiint(v)), dpp_shift<DPP_WAVE_SHR1>(__double2loint(v)));
+}
 
 // Field accesses outside the step's row buffers (the metrics kernel) go
 // through a global-address-space pointer.  The batched kernels read their
