@@ -38,3 +38,14 @@ def test_traffic_only_for_the_profiled_source_and_shape():
         assert bench._traffic(key, rows, other) is None
         # counted traffic is positive and within 1.5x of the launch's algorithmic bytes
         assert 0 < e["bytes_per_launch"] <= 1.5 * e["algorithmic_bytes"]
+
+
+def test_iteration_caps_per_workload(monkeypatch):
+    """Time-to-tolerance workloads stop at 3 million iterations unless told
+    otherwise; the loss workload, whose slowest pair needs about 6.9 million
+    to reach 1e-6, keeps 0 here and uses its own cap of 10 million."""
+    for argv, cap in ((["--workload", "rgb"], 3_000_000), (["--workload", "batched"], 3_000_000),
+                      (["--workload", "loss"], 0), (["--workload", "loss", "--cap", "500"], 500),
+                      (["--workload", "rgb", "--cap", "7"], 7)):
+        monkeypatch.setattr(sys, "argv", ["bench.py"] + argv)
+        assert bench._parse().cap == cap, argv
