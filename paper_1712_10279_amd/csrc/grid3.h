@@ -11,8 +11,8 @@ namespace omt {
 
 // rows of the register tile one wavefront updates per slice
 constexpr int G3_ROWS = 4;
-// columns a wavefront stores: lanes 1..62 (lanes 0 and 63 are halo lanes)
-constexpr int G3_COLS = 62;
+// columns a wavefront stores: all 64 lanes, an aligned block of columns
+constexpr int G3_COLS = 64;
 
 template <typename R>
 struct Step3Args {
@@ -27,7 +27,7 @@ struct Step3Args {
     int32_t m, n, p, pitch;
     int32_t l;             // edges in use
     int32_t unorm, wnorm;
-    int32_t ncolw, nroww;  // waves across (62-column strips) and down (row tiles)
+    int32_t ncolw, nroww;  // waves across (64-column strips) and down (row tiles)
     int32_t zch, nzw;      // slices per wave and z chunks
     int32_t nwg;           // workgroups launched
     R mu, mu_h, nu, anu, tau, inv_h, ureg, wreg;

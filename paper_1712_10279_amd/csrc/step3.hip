@@ -5,13 +5,17 @@
 // between z and z+1, with the ghost components u_x(m-1,.,.), u_y(.,n-1,.),
 // u_z(.,.,p-1) zero.
 //
-// One wavefront owns a register tile of G3_ROWS rows by 64 columns and
-// marches it through a chunk of slices along z.  Lanes are columns (every
-// access is a coalesced row segment); lanes 0 and 63 are halo lanes that
-// only supply neighbours, so a wave stores 62 columns.  The tile carries one
-// halo row above (its flux update gives the u_x neighbour of the first row)
-// and one below (its potential gives the gradient of the last row).  The
-// u_z neighbour of a slice is the previous slice's, kept in registers; a
+// One wavefront owns a register tile of G3_ROWS rows by 64 aligned columns
+// and marches it through a chunk of slices along z.  Lanes are columns
+// (every access is a coalesced row segment, and every store covers whole
+// cache lines).  The two neighbours from outside the tile come from side
+// loads in which lane c carries channel c: the potential right of the tile
+// (the u_y gradient of lane 63), and, left of it, the potential and flux
+// from which the left pixel's flux update is recomputed (the u_y divergence
+// of lane 0), with the same expressions as in its own tile.  The tile carries
+// one halo row above (its flux update gives the u_x neighbour of the first
+// row) and one below (its potential gives the gradient of the last row).
+// The u_z neighbour of a slice is the previous slice's, kept in registers; a
 // chunk starts one slice early to compute it.  Every pixel is computed by
 // the same expressions wherever it sits in a tile, so any tiling gives the
 // same iterates bit for bit.
@@ -77,17 +81,23 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(con
     const int wr = __builtin_amdgcn_readfirstlane((g / a.ncolw) % a.nroww);
     const int wz = __builtin_amdgcn_readfirstlane(g / (a.ncolw * a.nroww));
 
-    const int j = wc * G3_COLS - 1 + lane;
-    const bool jin = j >= 0 && j < a.n;
-    const bool jst = jin && lane >= 1 && lane <= G3_COLS;
+    const int j = wc * G3_COLS + lane;
+    const bool jin = j < a.n;
     const bool last_col = j == a.n - 1;
+    // side columns: jL left of the tile, jR right of it; lane c < K reads
+    // channel c there (plane c), other lanes read nothing
+    const int jL = wc * G3_COLS - 1, jR = wc * G3_COLS + G3_COLS;
+    const bool hasL = jL >= 0, hasR = jR < a.n;
+    const unsigned hcP = unsigned(lane < K ? lane : 0) * unsigned(a.plane);
+    const unsigned eL = lane < K && hasL ? (hcP + unsigned(jL)) * unsigned(sizeof(R)) : OFF_NONE;
+    const unsigned eR = lane < K && hasR ? (hcP + unsigned(jR)) * unsigned(sizeof(R)) : OFF_NONE;
     const int i0 = wr * RT;
     const int z0 = wz * a.zch, z1 = min(z0 + a.zch, a.p);
     const int zs = max(z0 - 1, 0);
     const int64_t P = a.plane;
     const unsigned Psz = unsigned(P) * unsigned(sizeof(R));
     const unsigned voff = jin ? unsigned(j) * unsigned(sizeof(R)) : OFF_NONE;
-    const unsigned soff = jst ? voff : OFF_NONE;  // stores, and the transfer loads of stored lanes only
+    const unsigned soff = voff;  // every lane in the grid stores
     const int nb_phi = field_bytes(K, P, a.n, sizeof(R)), nb_u = field_bytes(3 * K, P, a.n, sizeof(R));
     const int nb_w = field_bytes(a.l, P, a.n, sizeof(R));
     auto roff = [&](int z, int i) -> int64_t { return ((int64_t)z * a.m + i) * a.pitch; };
@@ -100,16 +110,22 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(con
     // of the current slice
     R ux[RT + 1][K], uy[RT + 1][K], uz[RT + 1][K];
     R wv[RT][LA], fv[RT][K];
+    // side values (lane c: channel c): the potential left and right of the
+    // tile on the current and the next slice, and the flux left of it
+    R eLc[RT + 2], eLn[RT + 2], eRc[RT + 2], eRn[RT + 2];
+    R eUx[RT + 1], eUy[RT + 1], eUz[RT + 1];
 #pragma unroll
     for (int q = 0; q < RT; ++q)
 #pragma unroll
         for (int c = 0; c < K; ++c) carry[q][c] = R(0);
     // loads of one row of a slice; ok = false gives a zero-length
     // descriptor (zeros, no memory access)
-    auto ld_phi = [&](R (&dst)[K], int z, int i, bool ok) {
+    auto ld_phi = [&](R (&dst)[K], R &dl, R &dr, int z, int i, bool ok) {
         const auto rp = row_rsrc(a.phi_in, roff(z, i), ok && row_ok(i) && z < a.p, nb_phi);
 #pragma unroll
         for (int c = 0; c < K; ++c) dst[c] = buf_ld<R>(rp, voff + unsigned(c) * Psz);
+        dl = buf_ld<R>(rp, eL);
+        dr = buf_ld<R>(rp, eR);
     };
     auto ld_u = [&](int q, int z, bool ok) {
         const int i = i0 - 1 + q;
@@ -120,6 +136,9 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(con
             uy[q][c] = buf_ld<R>(ru, voff + unsigned(K + c) * Psz);
             uz[q][c] = buf_ld<R>(ru, voff + unsigned(2 * K + c) * Psz);
         }
+        eUx[q] = buf_ld<R>(ru, eL);
+        eUy[q] = buf_ld<R>(ru, eL + unsigned(K) * Psz);
+        eUz[q] = buf_ld<R>(ru, eL + unsigned(2 * K) * Psz);
     };
     auto ld_wf = [&](int r, int z, bool ok) {
         const int i = i0 + r;
@@ -134,9 +153,9 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(con
     // the first slice: its potential, the next slice's, its fluxes, and
     // (if the wave stores it) its transfers and source
 #pragma unroll
-    for (int q = 0; q < RT + 2; ++q) ld_phi(pc[q], zs, i0 - 1 + q, true);
+    for (int q = 0; q < RT + 2; ++q) ld_phi(pc[q], eLc[q], eRc[q], zs, i0 - 1 + q, true);
 #pragma unroll
-    for (int q = 0; q < RT + 2; ++q) ld_phi(pn[q], zs + 1, i0 - 1 + q, true);
+    for (int q = 0; q < RT + 2; ++q) ld_phi(pn[q], eLn[q], eRn[q], zs + 1, i0 - 1 + q, true);
 #pragma unroll
     for (int q = 0; q < RT + 1; ++q) ld_u(q, zs, true);
 #pragma unroll
@@ -161,7 +180,8 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(con
             R tx[K], ty[K], tz[K];
 #pragma unroll
             for (int c = 0; c < K; ++c) {
-                const R pr = lane_next(pc[q][c]);
+                R pr = lane_next(pc[q][c]);
+                if (lane == WAVE - 1) pr = lane_get(eRc[q], c);
                 tx[c] = last_row ? R(0) : ux[q][c] + a.mu_h * (pc[q + 1][c] - pc[q][c]);
                 ty[c] = last_col ? R(0) : uy[q][c] + a.mu_h * (pr - pc[q][c]);
                 tz[c] = zlast ? R(0) : uz[q][c] + a.mu_h * (pn[q][c] - pc[q][c]);
@@ -180,6 +200,26 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(con
             if (q >= 1) {
                 const int r = q - 1;
                 if (inner) {
+                    // the pixel left of the tile: its flux update, as in
+                    // its own tile, for the u_y divergence of lane 0
+                    R lb[K];
+                    {
+                        R ex[K], ey[K], ez[K];
+#pragma unroll
+                        for (int c = 0; c < K; ++c) {
+                            const R hA = lane_get(eLc[q], c), hB = lane_get(eLc[q + 1], c);
+                            const R hZ = lane_get(eLn[q], c), hR = lane_get(pc[q][c], 0);
+                            ex[c] = last_row ? R(0) : lane_get(eUx[q], c) + a.mu_h * (hB - hA);
+                            ey[c] = lane_get(eUy[q], c) + a.mu_h * (hR - hA);  // never the last column
+                            ez[c] = zlast ? R(0) : lane_get(eUz[q], c) + a.mu_h * (hZ - hA);
+                        }
+                        shrink3<R, K>(a.unorm, ex, ey, ez, a.mu);
+#pragma unroll
+                        for (int c = 0; c < K; ++c) {
+                            const R yl = hasL ? ey[c] * a.ureg : R(0);
+                            lb[c] = R(2) * yl - (hasL ? lane_get(eUy[q], c) : R(0));
+                        }
+                    }
                     const bool st = rin;
                     const int64_t ro = roff(z, i);
                     const auto rphi = row_rsrc(a.phi_out, ro, st, nb_phi);
@@ -212,7 +252,8 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(con
                     // phi-update: phi + tau (div_x u_bar + div_G w_bar + f)
 #pragma unroll
                     for (int c = 0; c < K; ++c) {
-                        const R ubl = lane_prev(uby[c]);
+                        R ubl = lane_prev(uby[c]);
+                        if (lane == 0) ubl = lb[c];
                         const R dx = ((((ubx[c] - ubxp[c]) + uby[c]) - ubl) + (ubz[c] - carry[r][c])) * a.inv_h;
                         R dg = R(0);
                         if constexpr (L > 0) {
@@ -244,11 +285,15 @@ __global__ __launch_bounds__(WAVE *STEP_WAVES_PER_WG) void pdhg_step3_kernel(con
             if (q >= 1) ld_wf(q - 1, z + 1, more);
 #pragma unroll
             for (int c = 0; c < K; ++c) pc[q][c] = pn[q][c];
-            ld_phi(pn[q], z + 2, i0 - 1 + q, more);
+            eLc[q] = eLn[q];
+            eRc[q] = eRn[q];
+            ld_phi(pn[q], eLn[q], eRn[q], z + 2, i0 - 1 + q, more);
         }
 #pragma unroll
         for (int c = 0; c < K; ++c) pc[RT + 1][c] = pn[RT + 1][c];
-        ld_phi(pn[RT + 1], z + 2, i0 + RT, more);
+        eLc[RT + 1] = eLn[RT + 1];
+        eRc[RT + 1] = eRn[RT + 1];
+        ld_phi(pn[RT + 1], eLn[RT + 1], eRn[RT + 1], z + 2, i0 + RT, more);
     }
 }
 
