@@ -4,8 +4,8 @@ FP64 runs must match the oracle element by element to 1e-9 (relative to the
 largest entry), which catches any indexing or ordering mistake; FP32 runs
 must match V to 1e-4 relative and the exported potential Phi (mean removed
 per mass class) to 1e-3 max-abs at equal iteration counts and equal tau.
-Sizes span several wavefront strips (62 columns each at T = 1) and chunks
-of rows with ragged tails.
+Sizes span several wavefront strips (64 aligned columns each at T = 1,
+64 - 2T at T > 1) and chunks of rows with ragged tails.
 """
 import numpy as np
 import pytest
